@@ -1,0 +1,161 @@
+/*
+ * luqr.h -- C ABI of the MI355X hybrid LU-QR dense solver.
+ *
+ * Method: Faverge, Herrmann, Langou, Lowery, Robert, Dongarra, "Designing
+ * LU-QR hybrid solvers for performance and stability" (arXiv 1401.5522).
+ * At each panel step k of a tiled factorization (Alg. 1) the diagonal tile is
+ * factored with partial pivoting on a copy, a robustness criterion on tile
+ * norms (Sec. 3: Max, Sum, MUMPS) decides, on the device, between an LU step
+ * (Alg. 2, variant A1: GETRF / TRSM / SWPTRSM / GEMM) and a QR step (Alg. 3
+ * and 4a with a flat tree of TS kernels: GEQRT / TSQRT / UNMQR / TSMQR); the
+ * solve replays the stored transformations on the right-hand sides and
+ * back-substitutes (Sec. 2.4).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are column-major.  "Device pointer" means memory the HIP
+ *    runtime can access from the GPU the calling thread has current
+ *    (hipMalloc or torch CUDA tensors); "host pointer" means ordinary memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call only enqueues work on it and returns without waiting, except
+ *    the luqr_get_* calls, which wait for the stream.
+ *  - The library never allocates device memory: the caller provides one
+ *    workspace whose size luqr_workspace_bytes reports and keeps it alive
+ *    until luqr_destroy.  The library owns only the small host handle.
+ *  - Return codes: 0 = success; -i = argument i (1-based) is invalid;
+ *    LUQR_ERR_UNSUPPORTED for a valid but unimplemented combination;
+ *    LUQR_ERR_HIP - e for a HIP runtime error e.  Numerical conditions
+ *    (zero pivot, non-finite criterion input, refinement not converged) are
+ *    found on the device and reported by luqr_get_status; results are still
+ *    written, as LAPACK's getrf does.
+ */
+#ifndef LUQR_H
+#define LUQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LUQR_ERR_UNSUPPORTED (-900)
+#define LUQR_ERR_HIP (-1000)
+
+/* Robustness criterion of a panel step (Sec. 3). */
+typedef enum {
+    LUQR_CRIT_MAX = 0,    /* LU iff alpha/||A_kk^-1||_1 >= max_{i>k} ||A_ik||_1   (Sec. 3.1) */
+    LUQR_CRIT_SUM = 1,    /* LU iff alpha/||A_kk^-1||_1 >= sum_{i>k} ||A_ik||_1   (Sec. 3.2) */
+    LUQR_CRIT_MUMPS = 2,  /* LU iff alpha pivot(j) >= estimate_max(j) for all j   (Sec. 3.3) */
+    LUQR_CRIT_RANDOM = 3, /* LU with probability alpha/100 (the random choice of Sec. 5.2);
+                             draw k = SplitMix64 output k of `seed`, top 53 bits / 2^53 */
+    LUQR_CRIT_FORCED = 4  /* decisions given in opts.forced (1 = LU, 0 = QR) */
+} luqr_criterion;
+
+/* Arithmetic of the trailing contractions (GEMM update of LU steps, TSMQR
+ * update of QR steps) and of the stored factors.  The diagonal-tile GETRF,
+ * the inverse norm and all criterion norms are FP64 in every mode. */
+typedef enum {
+    LUQR_FP64 = 0, /* everything in FP64 */
+    LUQR_FP32 = 1, /* FP32 factor storage, FP32 MFMA contractions */
+    LUQR_BF16 = 2  /* FP32 factor storage, BF16 MFMA contraction operands with a
+                      power-of-two scale per tile, FP32 accumulation */
+} luqr_precision;
+
+typedef struct {
+    int32_t nb;          /* tile size n_b: 32, 64, 128, 256 or 512 (512 not with FP64) */
+    int32_t criterion;   /* luqr_criterion */
+    double alpha;        /* threshold alpha >= 0; +inf = always LU, 0 = always QR */
+    int32_t precision;   /* luqr_precision */
+    int32_t nrhs_max;    /* largest nrhs later passed to luqr_solve / luqr_solve_refined (>= 1) */
+    uint64_t seed;       /* LUQR_CRIT_RANDOM stream */
+    const int8_t *forced;/* host pointer, n = ceil(N/nb) decisions, read by luqr_factor (FORCED only) */
+    int32_t nsteps;      /* run only the first nsteps panel steps (< 0: all); a partial
+                            factorization cannot be solved with */
+    int32_t mumps_reading; /* 0 (default): estimate_max(j) = away_max(j) * prod_{i<j} growth(i) */
+} luqr_opts;
+
+/* Device-side numerical status, read back by luqr_get_status. */
+typedef struct {
+    int64_t info;        /* first exactly-zero pivot of an LU step, 1-based global row; 0 if none */
+    int32_t nonfinite;   /* a criterion input (s_k or m_k) was NaN or Inf at some step */
+    int32_t n_lu;        /* number of LU steps taken */
+    int32_t ir_iters;    /* refinement iterations done by the last luqr_solve_refined */
+    int32_t ir_converged;/* 1 if the last refinement met its backward-error target */
+    double ir_eta;       /* backward error ||b-Ax||_inf/(||A||_inf ||x||_inf) of the returned x
+                            (largest over right-hand sides) */
+    int32_t watchdog;    /* a device-side wait exceeded its spin bound (result invalid) */
+    int32_t reserved;
+} luqr_status;
+
+typedef struct luqr_factors_s *luqr_factors;
+
+/* Bytes of device workspace luqr_factor needs for an N x N matrix with the
+ * given options.  Returns < 0 (an argument code as above) on invalid input. */
+int64_t luqr_workspace_bytes(int64_t N, const luqr_opts *opts);
+
+/* Factor the N x N matrix dA (device, column-major, leading dimension lda,
+ * FP64, not modified) with the hybrid LU-QR algorithm (Alg. 1).  Factors,
+ * decisions and all scratch live in dWork (device, >= luqr_workspace_bytes,
+ * 256-byte aligned).  On success *out receives a new handle.  Asynchronous:
+ * returns once the work is enqueued on `stream`.  The decision of step k is
+ * written on the device and read there by the LU and QR branch kernels: the
+ * host never waits for it. */
+int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_opts *opts,
+                void *dWork, int64_t work_bytes, void *stream, luqr_factors *out);
+
+/* Overwrite dB (device, N x nrhs, leading dimension ldb, FP64) with A^{-1} B
+ * using the stored factors: forward replay of the step transformations
+ * (Sec. 2.4, second pass) then block back-substitution.  The arithmetic is
+ * the factor precision; B and the result are FP64.  nrhs <= opts.nrhs_max. */
+int luqr_solve(luqr_factors f, int64_t nrhs, double *dB, int64_t ldb, void *stream);
+
+/* Mixed-precision solve with FP64 iterative refinement: x0 = solve(b), then
+ * up to max_iter times r = b - A x (FP64, from dA), d = solve(r) in the factor
+ * precision, x += d (FP64), stopping on the device once every column has
+ * ||r||_inf <= N * 1e-16 * ||A||_inf ||x||_inf.  dA is the FP64 matrix that
+ * was factored; dB is read, dX (N x nrhs, ldx) written.  Iteration count and
+ * final backward error are reported by luqr_get_status. */
+int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda, int64_t nrhs,
+                       const double *dB, int64_t ldb, double *dX, int64_t ldx,
+                       int32_t max_iter, void *stream);
+
+/* Copy the decision sequence (1 = LU, 0 = QR), s_k = 1/||A_kk^-1||_1, m_k (the
+ * max or sum of sub-diagonal tile norms) and the relative margin
+ * (alpha s_k - m_k)/max(alpha s_k, m_k) of the first n steps to host arrays
+ * (each may be NULL).  Waits for the handle's stream. */
+int luqr_get_decisions(luqr_factors f, int8_t *dec, double *s, double *m, double *margin, int64_t n);
+
+/* Read the device status (waits for the handle's stream). */
+int luqr_get_status(luqr_factors f, luqr_status *st);
+
+/* Copy the factored matrix to dF (device, FP64, N x N, column-major, ldf) in
+ * the layout the paper describes in-place (L\U or V\R on the diagonal tiles,
+ * L or Y below, U_kj to the right), the LU pivots of every step to the host
+ * array ipiv (N entries, local 0-based row exchanged at each column; identity
+ * for QR steps; may be NULL).  For inspection and tests. */
+int luqr_export_factors(luqr_factors f, double *dF, int64_t ldf, int32_t *ipiv, void *stream);
+
+/* Release the host handle (the workspace belongs to the caller). */
+void luqr_destroy(luqr_factors f);
+
+/* ---- many independent systems ------------------------------------------ */
+
+/* Workspace for luqr_batched_solve of `batch` systems of sizes N[s] (host). */
+int64_t luqr_batched_workspace_bytes(int64_t batch, const int64_t *N, int64_t nrhs, const luqr_opts *opts);
+
+/* Solve batch independent systems A_s x_s = b_s in one persistent launch.
+ * N, lda, ldb, ldx are host arrays; dA, dB, dX are device arrays of device
+ * pointers (one per system, FP64, column-major).  opts.nb is the tile size
+ * (32 or 64); the precision, criterion and alpha apply to every system.
+ * With precision != FP64 the solution is refined in FP64 (up to max_iter
+ * iterations).  dDec (device, may be NULL) receives the decisions of system s
+ * at dDec + s * ceil(Nmax/nb); dEta (device, may be NULL) the backward error
+ * of each system. */
+int luqr_batched_solve(int64_t batch, const int64_t *N, const double *const *dA, const int64_t *lda,
+                       const double *const *dB, const int64_t *ldb, double *const *dX, const int64_t *ldx,
+                       int64_t nrhs, const luqr_opts *opts, int32_t max_iter, int8_t *dDec, double *dEta,
+                       void *dWork, int64_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LUQR_H */

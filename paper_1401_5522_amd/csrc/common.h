@@ -1,0 +1,234 @@
+// Shared device helpers and the workspace layout of the MI355X hybrid LU-QR
+// solver.  Everything here targets gfx950 (CDNA4): 64-lane wavefronts,
+// 256-thread workgroups (4 waves), MFMA 16x16 tiles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/luqr.h"
+
+#define LQ_DEV __device__ __forceinline__
+#define LQ_HD __host__ __device__ __forceinline__
+
+namespace lq {
+
+constexpr int WG = 256;    // threads per workgroup
+constexpr int IB = 32;     // inner block of panel factorizations and compact-WY factors
+constexpr int WAVE = 64;
+
+enum Prec { P64 = 0, P32 = 1, PB16 = 2 };
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// Per-precision traits.  S = storage type of the factors, C = compute type of
+// the trailing contractions (operands as MFMA sees them), acc = accumulator.
+// MFMA 16x16 layout used everywhere (lane l, accumulator register r):
+//   A operand:  row l%16,  k = KPL*(l/16) + e  (e < KPL)
+//   B operand:  col l%16,  k = KPL*(l/16) + e
+//   D / C:      row drow(l/16, r), col l%16, where drow(g, r) = 4g + r for
+//               the FP32-accumulating forms and g + 4r for f64 16x16x4
+//               (measured on gfx950 with a lane-layout probe)
+// KPL = 1 (f64, f32: k-step of 4) or 8 (bf16: k-step of 32).
+// ---------------------------------------------------------------------------
+template <int P> struct Tr;
+template <> struct Tr<P64> {
+    typedef double S; typedef double C; typedef d4 acc; typedef double frag;
+    static constexpr int KPL = 1;
+    static LQ_DEV int drow(int g, int r) { return g + 4 * r; }
+    static LQ_DEV acc mma(frag a, frag b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <> struct Tr<P32> {
+    typedef float S; typedef float C; typedef f4 acc; typedef float frag;
+    static constexpr int KPL = 1;
+    static LQ_DEV int drow(int g, int r) { return 4 * g + r; }
+    static LQ_DEV acc mma(frag a, frag b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <> struct Tr<PB16> {
+    typedef float S; typedef __bf16 C; typedef f4 acc; typedef bf8 frag;
+    static constexpr int KPL = 8;
+    static LQ_DEV int drow(int g, int r) { return 4 * g + r; }
+    static LQ_DEV acc mma(frag a, frag b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+
+template <class A> LQ_DEV A zero_acc() { A z; for (int r = 0; r < 4; ++r) z[r] = 0; return z; }
+
+LQ_DEV int lane_id() { return threadIdx.x & 63; }
+LQ_DEV int wave_id() { return threadIdx.x >> 6; }
+
+// ---- wave reductions (64 lanes) -------------------------------------------
+LQ_DEV double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+LQ_DEV float wave_sum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+LQ_DEV double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// argmax of |value| with the smallest index winning ties; NaN never wins.
+LQ_DEV void wave_argmax(double &v, int &idx) {
+    for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_xor(v, o, 64);
+        int oi = __shfl_xor(idx, o, 64);
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+}
+
+// Order LDS traffic between lanes of one wave (no workgroup barrier).
+LQ_DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- cross-workgroup flags (agent scope) -----------------------------------
+LQ_DEV void flag_publish(int *f, int v) {
+    __atomic_thread_fence(__ATOMIC_RELEASE);  // make prior writes of this thread visible
+    __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Spin until *f >= v.  Returns false if the spin bound is exhausted.
+LQ_DEV bool flag_wait(const int *f, int v, int *watchdog) {
+    long spins = 0;
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1L << 26)) {
+            __hip_atomic_store(watchdog, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if (__hip_atomic_load(watchdog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    return true;
+}
+
+// ---- conversions -----------------------------------------------------------
+template <class T> LQ_DEV T cvt(double x);
+template <> LQ_DEV double cvt<double>(double x) { return x; }
+template <> LQ_DEV float cvt<float>(double x) { return (float)x; }
+template <> LQ_DEV __bf16 cvt<__bf16>(double x) { return (__bf16)(float)x; }
+
+// ---------------------------------------------------------------------------
+// Device status word.
+// ---------------------------------------------------------------------------
+struct DevStatus {
+    long long info;      // first zero pivot (1-based global row) in an LU step
+    int nonfinite;
+    int n_lu;
+    int ir_iters;
+    int ir_converged;
+    double ir_eta;
+    int watchdog;
+    int pad;
+};
+
+// ---------------------------------------------------------------------------
+// Workspace layout.  All tiles are nb x nb, column-major, tile-major order:
+// tile (i,j) of an n x n tile grid starts at (j*n + i)*nb*nb elements.  The
+// matrix is padded to Np = n*nb with an identity block, so every kernel works
+// on full tiles (the clean-up case of Sec. 2.4 then costs nothing).
+// ---------------------------------------------------------------------------
+struct Layout {
+    int64_t N, n, nb, Np;
+    int prec, nrhs_max;
+    int64_t sz_S;  // bytes of a storage element
+    size_t off_At, off_Tf, off_W, off_Linv, off_Dinv, off_ipiv, off_perm, off_zpiv;
+    size_t off_dec, off_s, off_m, off_margin, off_status;
+    size_t off_tnorm, off_away, off_lmax, off_invpart, off_flags, off_scale;
+    size_t off_Y, off_Z, off_X, off_R, off_D, off_Xd, off_part, off_apart, off_rnorm, off_anorm, off_conv;
+    size_t total;
+    int64_t nparts;  // column chunks of the residual kernel
+};
+
+LQ_HD size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max) {
+    Layout L;
+    L.N = N; L.nb = nb; L.n = (N + nb - 1) / nb; L.Np = L.n * nb;
+    L.prec = prec; L.nrhs_max = nrhs_max < 1 ? 1 : nrhs_max;
+    L.sz_S = prec == P64 ? 8 : 4;
+    const size_t n = L.n, b = nb, t2 = b * b;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    L.off_At = take(n * n * t2 * L.sz_S);
+    L.off_Tf = take(n * n * b * IB * L.sz_S);
+    L.off_W = take(n * t2 * 8);
+    L.off_Linv = take(n * t2 * 8);
+    L.off_Dinv = take(n * t2 * 8);
+    L.off_ipiv = take(n * b * 4);
+    L.off_perm = take(n * b * 4);
+    L.off_zpiv = take(n * 4);
+    L.off_dec = take(n * 4);
+    L.off_s = take(n * 8);
+    L.off_m = take(n * 8);
+    L.off_margin = take(n * 8);
+    L.off_status = take(sizeof(DevStatus));
+    L.off_tnorm = take(n * 8);
+    L.off_away = take(n * b * 8);
+    L.off_lmax = take(b * 8);
+    L.off_invpart = take((b / 16 + 1) * b * 8);
+    L.off_flags = take((n + 2) * 4);
+    L.off_scale = take(n * n * 4);
+    const size_t Np = L.Np, r = L.nrhs_max;
+    L.off_Y = take(Np * r * 8);
+    L.off_Z = take(Np * r * 8);
+    L.off_X = take(Np * r * 8);
+    L.off_R = take(Np * r * 8);
+    L.off_D = take(Np * r * 8);
+    L.off_Xd = take(Np * r * 8);
+    L.nparts = (Np + 2047) / 2048;
+    L.off_part = take(L.nparts * Np * r * 8);
+    L.off_apart = take(L.nparts * Np * 8);
+    L.off_rnorm = take(r * 4 * 8);
+    L.off_anorm = take(8);
+    L.off_conv = take(16);
+    L.total = o;
+    return L;
+}
+
+// Device pointers into one workspace, passed by value to every kernel.
+struct Ctx {
+    void *At;        // factor tiles, storage precision
+    void *Tf;        // compact-WY T factors: tile (i,k) holds nb x IB (block b at rows b*IB)
+    double *W;       // per step: FP64 copy of A_kk, factored in place (L\U)
+    double *Linv;    // per step: L_kk^{-1} (unit lower)
+    double *Dinv;    // per step: inverse of the upper-triangular diagonal factor (U or R)
+    int *ipiv;       // per step: GETRF interchanges (local rows)
+    int *perm;       // per step: row permutation, (P A)(r,:) = A(perm[r],:)
+    int *zpiv;       // per step: first zero pivot of GETRF on the copy (1-based), 0 if none
+    int *dec;        // per step: 1 = LU, 0 = QR
+    double *s, *m, *margin;
+    DevStatus *st;
+    double *tnorm;   // per tile row i of the current panel: ||A_ik||_1
+    double *away;    // per tile row i: column maxima |A_ik(:,j)| (MUMPS)
+    double *lmax;    // column maxima of A_kk before factoring (MUMPS)
+    double *invpart; // partial column sums of |A_kk^{-1}| per 64-row block
+    int *flags;      // QR-step pipeline: flag[i] = k+1 once TSQRT(i,k) is published
+    unsigned *tmax;  // per tile: bit pattern of max |a| (BF16 scaling), tile-major index (j*n+i)
+    int64_t N, n;
+    int nb;
+    LQ_HD int64_t toff(int64_t i, int64_t j) const { return (j * n + i) * (int64_t)nb * nb; }
+    LQ_HD int msize(int64_t k) const { return (int)((k < n - 1) ? nb : N - (n - 1) * (int64_t)nb); }
+};
+
+inline Ctx make_ctx(const Layout &L, void *base) {
+    char *b = (char *)base;
+    Ctx c;
+    c.At = b + L.off_At; c.Tf = b + L.off_Tf; c.W = (double *)(b + L.off_W);
+    c.Linv = (double *)(b + L.off_Linv); c.Dinv = (double *)(b + L.off_Dinv);
+    c.ipiv = (int *)(b + L.off_ipiv); c.perm = (int *)(b + L.off_perm); c.zpiv = (int *)(b + L.off_zpiv);
+    c.dec = (int *)(b + L.off_dec); c.s = (double *)(b + L.off_s); c.m = (double *)(b + L.off_m);
+    c.margin = (double *)(b + L.off_margin); c.st = (DevStatus *)(b + L.off_status);
+    c.tnorm = (double *)(b + L.off_tnorm); c.away = (double *)(b + L.off_away);
+    c.lmax = (double *)(b + L.off_lmax); c.invpart = (double *)(b + L.off_invpart);
+    c.flags = (int *)(b + L.off_flags); c.tmax = (unsigned *)(b + L.off_scale);
+    c.N = L.N; c.n = L.n; c.nb = (int)L.nb;
+    return c;
+}
+
+}  // namespace lq

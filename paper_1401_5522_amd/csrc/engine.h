@@ -1,0 +1,86 @@
+// Host-side launch sequences.  The host enqueues every kernel of every step
+// on one stream without waiting: the LU-or-QR decision of step k is written
+// to device memory by k_panel_decide and both branch kernels read it there,
+// returning at once when they are not the chosen branch (the dynamic task
+// graph of Sec. 4 without a host round trip).
+#pragma once
+#include "lu.h"
+#include "panel.h"
+#include "qr.h"
+#include "solve.h"
+
+namespace lq {
+
+struct Ops {
+    void (*factor)(const Ctx &, const Layout &, const double *A, int64_t lda, const luqr_opts &, int nsteps,
+                   hipStream_t);
+    void (*solve)(const Ctx &, const Layout &, SolveArgs, hipStream_t);
+    void (*export_factors)(const Ctx &, const Layout &, double *F, int64_t ldf, hipStream_t);
+};
+
+inline unsigned nblk(int64_t count, int per = WG) { return (unsigned)((count + per - 1) / per); }
+
+template <int NB, int P>
+struct Eng {
+    typedef typename Tr<P>::S S;
+
+    static void factor(const Ctx &c, const Layout &L, const double *A, int64_t lda, const luqr_opts &o, int nsteps,
+                       hipStream_t st) {
+        const int n = (int)c.n;
+        k_status_reset<<<1, 64, 0, st>>>(c.st);
+        k_fill_int<<<nblk(n + 2), WG, 0, st>>>(c.flags, n + 2, 0);
+        k_fill_int<<<nblk(n), WG, 0, st>>>(c.dec, n, -1);
+        k_fill_u32<<<nblk((int64_t)n * n), WG, 0, st>>>(c.tmax, (int64_t)n * n);
+        k_to_tiles<S><<<nblk(L.Np * L.Np), WG, 0, st>>>(A, lda, c.N, c.n, NB, (S *)c.At);
+        constexpr int B = NB < 64 ? NB : 64;
+        for (int k = 0; k < nsteps; ++k) {
+            const int rest = n - k - 1;
+            k_panel_a<NB, S><<<n - k, WG, 0, st>>>(c, k);
+            k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
+            k_panel_invnorm<NB><<<(NB / B) * (NB / B), WG, 0, st>>>(c, k);
+            DecideArgs a;
+            a.crit = o.criterion;
+            a.alpha = o.alpha;
+            a.forced_k = (o.criterion == LUQR_CRIT_FORCED) ? o.forced[k] : 0;
+            a.seed = o.seed;
+            a.mumps_reading = o.mumps_reading;
+            k_panel_decide<NB><<<1, WG, 0, st>>>(c, k, a);
+            k_lu_apply<NB, P><<<1 + 2 * rest * (NB / lu_rb<NB>()), WG, 0, st>>>(c, k);
+            if (rest > 0) {
+                constexpr int PER = NB / upd_bt<NB>();
+                k_lu_update<NB, P><<<(unsigned)rest * rest * PER * PER, WG, 0, st>>>(c, k);
+            }
+            k_qr_step<NB, P><<<1 + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
+            k_qr_rinv<NB, S><<<NB / 4, WG, 0, st>>>(c, k);
+        }
+    }
+
+    static void solve(const Ctx &c, const Layout &L, SolveArgs s, hipStream_t st) {
+        const int n = (int)c.n;
+        const unsigned ch = (unsigned)((s.nrhs + RQ - 1) / RQ);
+        for (int k = 0; k < n; ++k) {
+            k_fwd_lu_a<NB><<<dim3(1, ch), WG, 0, st>>>(c, s, k);
+            if (n - k - 1 > 0) k_fwd_lu_b<NB, S><<<dim3(n - k - 1, ch), WG, 0, st>>>(c, s, k);
+            k_fwd_qr<NB, S><<<dim3(1, ch), WG, 0, st>>>(c, s, k);
+        }
+        for (int k = n - 1; k >= 0; --k) {
+            k_bwd_a<NB><<<dim3(1, ch), WG, 0, st>>>(c, s, k);
+            if (k > 0) k_bwd_b<NB, S><<<dim3(k, ch), WG, 0, st>>>(c, s, k);
+        }
+    }
+
+    static void export_factors(const Ctx &c, const Layout &L, double *F, int64_t ldf, hipStream_t st) {
+        k_from_tiles<S><<<nblk(c.N * c.N), WG, 0, st>>>((const S *)c.At, c.n, NB, c.N, F, ldf);
+    }
+
+    static const Ops *ops() {
+        static const Ops o = {&factor, &solve, &export_factors};
+        return &o;
+    }
+};
+
+const Ops *ops_p64(int nb);
+const Ops *ops_p32(int nb);
+const Ops *ops_pb16(int nb);
+
+}  // namespace lq

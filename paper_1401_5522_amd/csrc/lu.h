@@ -1,0 +1,134 @@
+// LU step, variant A1 (Alg. 2), run only when the device-side decision of
+// step k says LU:
+//   Factor   A_kk <- L\U from the GETRF copy,
+//   Eliminate A_ik <- A_ik U^{-1}      (i > k),
+//   Apply     A_kj <- L^{-1} P A_kj    (j > k),
+//   Update    A_ij <- A_ij - A_ik A_kj (i, j > k).
+// Eliminate and Apply multiply by the explicit triangular inverses computed
+// for the criterion, so all three are MFMA contractions; each in-place
+// product is computed by a workgroup that owns whole rows (Eliminate) or
+// whole columns (Apply) of the output, so it reads all of its input before
+// writing.
+#pragma once
+#include "mma.h"
+
+namespace lq {
+
+// Rows per Eliminate workgroup / columns per Apply workgroup: the output
+// block (RB x NB) holds 16K elements in registers.
+template <int NB> constexpr int lu_rb() { return NB >= 128 ? 16384 / NB : NB; }
+// Wave grid of the Eliminate block (RB x NB) and Apply block (NB x RB).
+template <int NB> constexpr int lu_wn() { return NB >= 64 ? 4 : 2; }
+
+template <int P> LQ_DEV float tile_scale(const Ctx &c, int64_t i, int64_t j) {
+    if constexpr (P != PB16) return 1.0f;
+    float mx = __uint_as_float(c.tmax[j * c.n + i]);
+    if (!(mx > 0.0f) || !isfinite(mx)) return 1.0f;
+    return ldexpf(1.0f, -ilogbf(mx));  // scaled max in [1, 2)
+}
+
+template <int NB, int P>
+__global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
+    if (c.dec[k] != 1) return;
+    typedef typename Tr<P>::S S;
+    constexpr int RB = lu_rb<NB>();
+    constexpr int WN = lu_wn<NB>(), WM = 4 / WN;
+    constexpr int BK = (P == PB16) ? 32 : 16;
+    __shared__ __attribute__((aligned(16))) char smem[mma_lds_bytes<P, (RB > NB ? RB : NB), (RB > NB ? RB : NB), BK>()];
+    __shared__ float wmax[WG / 64];
+    const int rest = (int)c.n - k - 1;
+    const int per_tile = NB / RB;
+    int b = blockIdx.x;
+    S *At = (S *)c.At;
+    if (b == 0) {  // commit the factored copy (L\U) to the diagonal tile
+        const double *W = c.W + (size_t)k * NB * NB;
+        S *Akk = At + c.toff(k, k);
+        for (int e = threadIdx.x; e < NB * NB; e += WG) Akk[e] = (S)W[e];
+        return;
+    }
+    b -= 1;
+    float lmx = 0.0f;
+    if (b < rest * per_tile) {  // Eliminate: rows [r0, r0+RB) of A_ik times U^{-1}
+        const int i = k + 1 + b / per_tile, r0 = (b % per_tile) * RB;
+        S *X = At + c.toff(i, k);
+        const double *Ui = c.Dinv + (size_t)k * NB * NB;
+        typename Tr<P>::acc acc[RB / WM / 16][NB / WN / 16];
+        acc_zero<P, RB, NB, WM, WN>(acc);
+        wg_mma<P, RB, NB, WM, WN, BK>(
+            acc, NB, [&](int r, int kk) { return (double)X[r0 + r + kk * NB]; },
+            [&](int kk, int cc) { return Ui[kk + (size_t)cc * NB]; }, smem);
+        __syncthreads();
+        acc_foreach<P, RB, NB, WM, WN>(acc, [&](int r, int cc, double v) {
+            S o = (S)v;
+            X[r0 + r + cc * NB] = o;
+            lmx = fmaxf(lmx, fabsf((float)o));
+        });
+        if constexpr (P == PB16) {
+            for (int o = 32; o > 0; o >>= 1) lmx = fmaxf(lmx, __shfl_xor(lmx, o, 64));
+            if (lane_id() == 0) atomicMax(&c.tmax[(size_t)k * c.n + i], __float_as_uint(lmx));
+        }
+        return;
+    }
+    b -= rest * per_tile;
+    {  // Apply: columns [c0, c0+RB) of A_kj <- L^{-1} (P A_kj)
+        const int j = k + 1 + b / per_tile, c0 = (b % per_tile) * RB;
+        S *X = At + c.toff(k, j);
+        const double *Li = c.Linv + (size_t)k * NB * NB;
+        const int *pm = c.perm + (size_t)k * NB;
+        typename Tr<P>::acc acc[NB / WN / 16][RB / WM / 16];
+        acc_zero<P, NB, RB, WN, WM>(acc);
+        wg_mma<P, NB, RB, WN, WM, BK>(
+            acc, NB, [&](int r, int kk) { return Li[r + (size_t)kk * NB]; },
+            [&](int kk, int cc) { return (double)X[pm[kk] + (c0 + cc) * NB]; }, smem);
+        __syncthreads();
+        acc_foreach<P, NB, RB, WN, WM>(acc, [&](int r, int cc, double v) {
+            S o = (S)v;
+            X[r + (c0 + cc) * NB] = o;
+            lmx = fmaxf(lmx, fabsf((float)o));
+        });
+        if constexpr (P == PB16) {
+            for (int o = 32; o > 0; o >>= 1) lmx = fmaxf(lmx, __shfl_xor(lmx, o, 64));
+            if (lane_id() == 0) atomicMax(&c.tmax[(size_t)j * c.n + k], __float_as_uint(lmx));
+        }
+    }
+    (void)wmax;
+}
+
+// Update: A_ij -= A_ik A_kj over the (n-k-1)^2 trailing tiles, BT x BT
+// output blocks per workgroup.  BF16 mode: operands are rounded to bf16
+// after scaling each tile by a power of two (its max |a| in [1,2)), the
+// product accumulates in FP32 and is scaled back exactly.
+template <int NB> constexpr int upd_bt() { return NB >= 128 ? 128 : NB; }
+
+template <int NB, int P>
+__global__ __launch_bounds__(WG) void k_lu_update(Ctx c, int k) {
+    if (c.dec[k] != 1) return;
+    typedef typename Tr<P>::S S;
+    constexpr int BT = upd_bt<NB>();
+    constexpr int BK = (P == PB16) ? 32 : 16;
+    constexpr int PER = NB / BT;
+    __shared__ __attribute__((aligned(16))) char smem[mma_lds_bytes<P, BT, BT, BK>()];
+    const int rest = (int)c.n - k - 1;
+    int b = blockIdx.x;
+    const int sub = b % (PER * PER);
+    const int t = b / (PER * PER);
+    const int i = k + 1 + t % rest, j = k + 1 + t / rest;
+    const int r0 = (sub % PER) * BT, c0 = (sub / PER) * BT;
+    S *At = (S *)c.At;
+    const S *Aik = At + c.toff(i, k);
+    const S *Akj = At + c.toff(k, j);
+    S *Cij = At + c.toff(i, j);
+    const float sa = tile_scale<P>(c, i, k), sb = tile_scale<P>(c, k, j);
+    typename Tr<P>::acc acc[BT / 2 / 16][BT / 2 / 16];
+    acc_zero<P, BT, BT, 2, 2>(acc);
+    wg_mma<P, BT, BT, 2, 2, BK>(
+        acc, NB, [&](int r, int kk) { return (double)Aik[r0 + r + kk * NB] * sa; },
+        [&](int kk, int cc) { return (double)Akj[kk + (c0 + cc) * NB] * sb; }, smem);
+    const double inv = 1.0 / ((double)sa * (double)sb);
+    acc_foreach<P, BT, BT, 2, 2>(acc, [&](int r, int cc, double v) {
+        S *p = Cij + (r0 + r) + (size_t)(c0 + cc) * NB;
+        *p = (S)((double)*p - v * inv);
+    });
+}
+
+}  // namespace lq
