@@ -5,7 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/luqr.h"
+#include "luqr.h"
 
 #define LQ_DEV __device__ __forceinline__
 #define LQ_HD __host__ __device__ __forceinline__
@@ -58,26 +58,48 @@ template <class A> LQ_DEV A zero_acc() { A z; for (int r = 0; r < 4; ++r) z[r] =
 LQ_DEV int lane_id() { return threadIdx.x & 63; }
 LQ_DEV int wave_id() { return threadIdx.x >> 6; }
 
-// ---- wave reductions (64 lanes) -------------------------------------------
-LQ_DEV double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// ---- lane exchanges and wave reductions (64 lanes) ---------------------------
+// Six partner maps whose composition reaches every lane: xor 32 and xor 16
+// (ds_bpermute across rows), then within each 16-lane row the DPP forms
+// row_mirror (i <-> 15-i), row_half_mirror (i <-> 7-i), quad xor 2, quad
+// xor 1.  Stage s flips lane bit 5-s (and only lower bits besides), so a
+// butterfly over the six stages sums each lane with all 63 others once.
+template <int CTRL> LQ_DEV int dpp_i(int x) { return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false); }
+template <int ST> LQ_DEV int xlane(int x) {
+    if constexpr (ST == 0) return __shfl_xor(x, 32, 64);
+    else if constexpr (ST == 1) return __shfl_xor(x, 16, 64);
+    else if constexpr (ST == 2) return dpp_i<0x140>(x);  // row_mirror
+    else if constexpr (ST == 3) return dpp_i<0x141>(x);  // row_half_mirror
+    else if constexpr (ST == 4) return dpp_i<0x4E>(x);   // quad_perm [2,3,0,1]
+    else return dpp_i<0xB1>(x);                          // quad_perm [1,0,3,2]
 }
-LQ_DEV float wave_sum(float v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+template <int ST> LQ_DEV float xlane(float x) { return __int_as_float(xlane<ST>(__float_as_int(x))); }
+template <int ST> LQ_DEV double xlane(double x) {
+    const int lo = xlane<ST>(__double2loint(x)), hi = xlane<ST>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+// lane bit that distinguishes a lane from its stage-ST partner
+template <int ST> constexpr int xbit() { return 5 - ST; }
+
+template <class T> LQ_DEV T wave_sum(T v) {
+    v += xlane<0>(v); v += xlane<1>(v); v += xlane<2>(v);
+    v += xlane<3>(v); v += xlane<4>(v); v += xlane<5>(v);
     return v;
 }
 LQ_DEV double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    v = fmax(v, xlane<0>(v)); v = fmax(v, xlane<1>(v)); v = fmax(v, xlane<2>(v));
+    v = fmax(v, xlane<3>(v)); v = fmax(v, xlane<4>(v)); v = fmax(v, xlane<5>(v));
     return v;
+}
+template <int ST> LQ_DEV void argmax_step(double &v, int &idx) {
+    const double ov = xlane<ST>(v);
+    const int oi = xlane<ST>(idx);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
 }
 // argmax of |value| with the smallest index winning ties; NaN never wins.
 LQ_DEV void wave_argmax(double &v, int &idx) {
-    for (int o = 32; o > 0; o >>= 1) {
-        double ov = __shfl_xor(v, o, 64);
-        int oi = __shfl_xor(idx, o, 64);
-        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-    }
+    argmax_step<0>(v, idx); argmax_step<1>(v, idx); argmax_step<2>(v, idx);
+    argmax_step<3>(v, idx); argmax_step<4>(v, idx); argmax_step<5>(v, idx);
 }
 
 // Order LDS traffic between lanes of one wave (no workgroup barrier).
@@ -172,7 +194,7 @@ inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max) {
     L.off_away = take(n * b * 8);
     L.off_lmax = take(b * 8);
     L.off_invpart = take((b / 16 + 1) * b * 8);
-    L.off_flags = take((n + 2) * 4);
+    L.off_flags = take(n * (b / IB) * 4 + 64);
     L.off_scale = take(n * n * 4);
     const size_t Np = L.Np, r = L.nrhs_max;
     L.off_Y = take(Np * r * 8);
@@ -208,7 +230,7 @@ struct Ctx {
     double *away;    // per tile row i: column maxima |A_ik(:,j)| (MUMPS)
     double *lmax;    // column maxima of A_kk before factoring (MUMPS)
     double *invpart; // partial column sums of |A_kk^{-1}| per 64-row block
-    int *flags;      // QR-step pipeline: flag[i] = k+1 once TSQRT(i,k) is published
+    int *flags;      // QR-step pipeline: flag[i*(nb/IB) + b] = k+1 once block b of tile i's reflectors is published
     unsigned *tmax;  // per tile: bit pattern of max |a| (BF16 scaling), tile-major index (j*n+i)
     int64_t N, n;
     int nb;

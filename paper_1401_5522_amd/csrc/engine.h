@@ -28,7 +28,7 @@ struct Eng {
                        hipStream_t st) {
         const int n = (int)c.n;
         k_status_reset<<<1, 64, 0, st>>>(c.st);
-        k_fill_int<<<nblk(n + 2), WG, 0, st>>>(c.flags, n + 2, 0);
+        k_fill_int<<<nblk((int64_t)n * (NB / IB)), WG, 0, st>>>(c.flags, (int64_t)n * (NB / IB), 0);
         k_fill_int<<<nblk(n), WG, 0, st>>>(c.dec, n, -1);
         k_fill_u32<<<nblk((int64_t)n * n), WG, 0, st>>>(c.tmax, (int64_t)n * n);
         k_to_tiles<S><<<nblk(L.Np * L.Np), WG, 0, st>>>(A, lda, c.N, c.n, NB, (S *)c.At);
@@ -50,7 +50,7 @@ struct Eng {
                 constexpr int PER = NB / upd_bt<NB>();
                 k_lu_update<NB, P><<<(unsigned)rest * rest * PER * PER, WG, 0, st>>>(c, k);
             }
-            k_qr_step<NB, P><<<1 + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
+            k_qr_step<NB, P><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
             k_qr_rinv<NB, S><<<NB / 4, WG, 0, st>>>(c, k);
         }
     }

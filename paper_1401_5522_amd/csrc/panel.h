@@ -10,6 +10,8 @@
 //   * the decision itself (Sec. 3.1-3.3 and the random control of Sec. 5.2),
 //     written to device memory where the branch kernels read it.
 #pragma once
+#include <utility>
+
 #include "mma.h"
 
 namespace lq {
@@ -18,136 +20,273 @@ namespace lq {
 // treatment of non-finite norms).
 LQ_DEV double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
 LQ_DEV double wave_nmax(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = nmax(v, __shfl_xor(v, o, 64));
+    v = nmax(v, xlane<0>(v)); v = nmax(v, xlane<1>(v)); v = nmax(v, xlane<2>(v));
+    v = nmax(v, xlane<3>(v)); v = nmax(v, xlane<4>(v)); v = nmax(v, xlane<5>(v));
     return v;
 }
 
 // ---------------------------------------------------------------------------
 // GETRF of the diagonal tile on its FP64 copy W_k, one workgroup.
-// Blocked right-looking: each 32-column panel is staged in LDS and factored
-// by wave 0 with wave-level argmax (first index of the largest magnitude wins
-// ties); then all four waves apply the interchanges to the other columns,
-// solve U12 = L11^{-1} A12 and update A22 -= L21 U12.
+// Blocked right-looking LU with partial pivoting: each 32-column panel is
+// held in registers, thread t owning tile rows t and t+256, and factored one
+// column at a time (column q is its own instantiation, so register indices
+// are static): argmax over the workgroup (the first row holding the largest
+// magnitude wins ties), exchange of the two rows through LDS, scaling and
+// rank-1 update.  The panel's interchanges are then applied to the other
+// columns through LDS, U12 = L11^{-1} A12 is solved and A22 -= L21 U12.
 // ---------------------------------------------------------------------------
+template <int NB> constexpr int lu_rpt() { return NB > 256 ? 2 : 1; }
+
+struct GetrfLds {
+    double bv[4];
+    int bi[4];
+    int piv[32];
+    int zp;
+    int tcnt;
+    int trow[64], tsrc[64];
+    double rowA[32], rowB[32];
+};
+
+template <int NB, int Q>
+LQ_DEV void lu_column(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g) {
+    constexpr int RPT = lu_rpt<NB>();
+    const int tid = threadIdx.x, l = lane_id(), w = wave_id();
+    const int col = p0 + Q;
+    double v = -1.0;
+    int idx = 0x7fffffff;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {  // rows ascending within the thread
+        const int r = tid + 256 * u;
+        if (r >= col && r < NB) {
+            const double a = fabs(P[u][Q]);
+            if (a > v) { v = a; idx = r; }
+        }
+    }
+    wave_argmax(v, idx);
+    if (l == 0) { g->bv[w] = v; g->bi[w] = idx; }
+    __syncthreads();  // A
+    v = g->bv[0];
+    idx = g->bi[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+        const double ov = g->bv[q];
+        const int oi = g->bi[q];
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    const bool zero = !(v > 0.0);  // exactly zero (or non-numeric) column: no elimination
+    const int piv = zero ? col : idx;
+    if (tid == 0) {
+        g->piv[Q] = piv;
+        if (zero && g->zp == 0) g->zp = col + 1;
+    }
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int r = tid + 256 * u;
+        if (r == col) {
+#pragma unroll
+            for (int j = 0; j < 32; ++j) g->rowA[j] = P[u][j];
+        }
+        if (r == piv) {
+#pragma unroll
+            for (int j = 0; j < 32; ++j) g->rowB[j] = P[u][j];
+        }
+    }
+    __syncthreads();  // B: rows col and piv exchanged through LDS
+    if (!zero) {
+        const double pv = g->rowB[Q];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int r = tid + 256 * u;
+            if (r == col) {
+#pragma unroll
+                for (int j = 0; j < 32; ++j) P[u][j] = g->rowB[j];
+            } else if (r == piv) {
+#pragma unroll
+                for (int j = 0; j < 32; ++j) P[u][j] = g->rowA[j];
+            }
+            if (r > col && r < NB) {
+                const double lr = P[u][Q] / pv;
+                P[u][Q] = lr;
+#pragma unroll
+                for (int j = Q + 1; j < 32; ++j) P[u][j] -= lr * g->rowB[j];
+            }
+        }
+    }
+}
+
+template <int NB, int... Qs>
+LQ_DEV void lu_columns(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g, std::integer_sequence<int, Qs...>) {
+    (lu_column<NB, Qs>(P, p0, g), ...);
+}
+
 template <int NB, class S>
 LQ_DEV void getrf_diag(const Ctx &c, int k) {
-    __shared__ double P[32 * NB];   // panel column j at P[j*NB + r] (rows >= p0 used)
-    __shared__ double Us[32 * 33];  // 32 x 32 chunk of U12
-    __shared__ int piv[32];
-    __shared__ int zp;
+    constexpr int RPT = lu_rpt<NB>();
+    constexpr int BUFN = NB <= 256 ? 32 * (NB + 1) + NB * 33 : 32 * 33;
+    __shared__ double buf[BUFN];           // L21 / U12 staging of the trailing update
+    __shared__ double L11[32 * 33];
+    __shared__ int src[NB];
+    __shared__ unsigned long long lmx[NB];
+    __shared__ GetrfLds g;
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
     double *W = c.W + (size_t)k * NB * NB;
     const S *A = (const S *)c.At + c.toff(k, k);
-    for (int e = tid; e < NB * NB; e += WG) W[e] = (double)A[e];
-    for (int col = w; col < NB; col += 4) {
-        double v = 0.0;
-        for (int r = l; r < NB; r += 64) v = nmax(v, fabs((double)A[r + col * NB]));
-        v = wave_nmax(v);
-        if (l == 0) c.lmax[col] = v;
-    }
-    if (tid == 0) zp = 0;
+    for (int e = tid; e < NB; e += WG) lmx[e] = 0ull;
+    if (tid == 0) g.zp = 0;
     __syncthreads();
-    for (int p0 = 0; p0 < NB; p0 += 32) {
-        const int H = NB - p0;
-        for (int e = tid; e < H * 32; e += WG) {
-            int r = p0 + e % H, j = e / H;
-            P[j * NB + r] = W[r + (p0 + j) * NB];
+    // copy A_kk -> W (FP64) and its column maxima (MUMPS local_max)
+    for (int e0 = 0; e0 < NB * NB; e0 += 8 * WG) {
+        double a[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = e0 + t * WG + tid;
+            a[t] = e < NB * NB ? (double)A[e] : 0.0;
         }
-        __syncthreads();
-        if (w == 0) {
-            for (int cc = 0; cc < 32; ++cc) {
-                const int col = p0 + cc;
-                double v = -1.0;
-                int idx = 0x7fffffff;
-                for (int r = col + l; r < NB; r += 64) {
-                    double a = fabs(P[cc * NB + r]);
-                    if (a > v) { v = a; idx = r; }
-                }
-                wave_argmax(v, idx);
-                if (!(v > 0.0)) {  // exactly zero (or non-numeric) column: no elimination
-                    if (l == 0) { piv[cc] = col; if (zp == 0) zp = col + 1; }
-                    wave_sync();
-                    continue;
-                }
-                if (l == 0) piv[cc] = idx;
-                if (idx != col && l < 32) {
-                    double t = P[l * NB + col];
-                    P[l * NB + col] = P[l * NB + idx];
-                    P[l * NB + idx] = t;
-                }
-                wave_sync();
-                const double pv = P[cc * NB + col];
-                for (int r = col + 1 + l; r < NB; r += 64) P[cc * NB + r] /= pv;
-                wave_sync();
-                for (int j = cc + 1; j < 32; ++j) {
-                    const double u = P[j * NB + col];
-                    for (int r = col + 1 + l; r < NB; r += 64) P[j * NB + r] -= P[cc * NB + r] * u;
-                }
-                wave_sync();
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = e0 + t * WG + tid;
+            if (e < NB * NB) W[e] = a[t];
+            double m = fabs(a[t]);
+            m = wave_nmax(m);  // a wave covers 64 consecutive rows of one column
+            if (l == 0 && e < NB * NB) atomicMax(&lmx[e / NB], (unsigned long long)__double_as_longlong(m));
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < NB; e += WG) c.lmax[e] = __longlong_as_double((long long)lmx[e]);
+    for (int p0 = 0; p0 < NB; p0 += 32) {
+        double P[RPT][32];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int r = tid + 256 * u;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) P[u][j] = (r >= p0 && r < NB) ? W[r + (p0 + j) * NB] : 0.0;
+        }
+        lu_columns<NB>(P, p0, &g, std::make_integer_sequence<int, 32>{});
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int r = tid + 256 * u;
+            if (r >= p0 && r < NB) {
+#pragma unroll
+                for (int j = 0; j < 32; ++j) W[r + (p0 + j) * NB] = P[u][j];
+            }
+            if (r >= p0 && r < p0 + 32) {
+#pragma unroll
+                for (int j = 0; j < 32; ++j) L11[j * 33 + (r - p0)] = P[u][j];
             }
         }
-        __syncthreads();
-        for (int e = tid; e < H * 32; e += WG) {
-            int r = p0 + e % H, j = e / H;
-            W[r + (p0 + j) * NB] = P[j * NB + r];
+        if (tid < 32) c.ipiv[(size_t)k * NB + p0 + tid] = g.piv[tid];
+        // rows moved by the panel's interchanges: trow[t] receives row tsrc[t]
+        if (tid == 0) {
+            for (int r = p0; r < NB; ++r) src[r] = r;
+            for (int q = 0; q < 32; ++q) {
+                const int a = p0 + q, b = g.piv[q];
+                const int t = src[a]; src[a] = src[b]; src[b] = t;
+            }
+            int cnt = 0;
+            for (int q = 0; q < 32; ++q) {
+                const int a = p0 + q, b = g.piv[q];
+                if (src[a] != a) { g.trow[cnt] = a; g.tsrc[cnt] = src[a]; src[a] = a; ++cnt; }
+                if (b != a && src[b] != b) { g.trow[cnt] = b; g.tsrc[cnt] = src[b]; src[b] = b; ++cnt; }
+            }
+            g.tcnt = cnt;
         }
-        if (tid < 32) c.ipiv[(size_t)k * NB + p0 + tid] = piv[tid];
-        for (int col = tid; col < NB; col += WG) {
-            if (col >= p0 && col < p0 + 32) continue;
-            for (int cc = 0; cc < 32; ++cc) {
-                const int r = p0 + cc, pr = piv[cc];
-                if (pr != r) {
-                    double t = W[r + col * NB];
-                    W[r + col * NB] = W[pr + col * NB];
-                    W[pr + col * NB] = t;
-                }
+        __syncthreads();
+        {
+            const int cnt = g.tcnt;
+            for (int cc = tid; cc < NB; cc += WG) {  // columns outside the panel
+                if (cc >= p0 && cc < p0 + 32) continue;
+                double v[64];
+#pragma unroll
+                for (int t = 0; t < 64; ++t) v[t] = t < cnt ? W[g.tsrc[t] + cc * NB] : 0.0;
+#pragma unroll
+                for (int t = 0; t < 64; ++t)
+                    if (t < cnt) W[g.trow[t] + cc * NB] = v[t];
             }
         }
         __syncthreads();
         if (p0 + 32 < NB) {
-            for (int col = p0 + 32 + tid; col < NB; col += WG) {  // U12 = L11^{-1} A12
+            for (int cc = p0 + 32 + tid; cc < NB; cc += WG) {  // U12 = L11^{-1} A12
                 double x[32];
 #pragma unroll
-                for (int q = 0; q < 32; ++q) x[q] = W[p0 + q + col * NB];
+                for (int q = 0; q < 32; ++q) x[q] = W[p0 + q + cc * NB];
 #pragma unroll
                 for (int q = 0; q < 32; ++q)
 #pragma unroll
-                    for (int r = q + 1; r < 32; ++r) x[r] -= P[q * NB + p0 + r] * x[q];
+                    for (int r = q + 1; r < 32; ++r) x[r] -= L11[q * 33 + r] * x[q];
 #pragma unroll
-                for (int q = 0; q < 32; ++q) W[p0 + q + col * NB] = x[q];
+                for (int q = 0; q < 32; ++q) W[p0 + q + cc * NB] = x[q];
             }
             __syncthreads();
-            for (int c0 = p0 + 32; c0 < NB; c0 += 32) {  // A22 -= L21 U12, 32 columns at a time
-                for (int e = tid; e < 32 * 32; e += WG) {
-                    int q = e % 32, j = e / 32;
-                    Us[j * 33 + q] = W[p0 + q + (c0 + j) * NB];
+            if constexpr (NB <= 256) {
+                // A22 -= L21 U12 on FP64 MFMA: L21 (rows p0+32.., 32 cols) and U12 (32 x
+                // trailing cols) staged in LDS, 16x16 output blocks spread over the waves
+                constexpr int LDL = NB + 1;
+                double *Ls = buf;                 // [32][LDL]
+                double *Ub = buf + 32 * LDL;      // [ncol][33]
+                const int r0 = p0 + 32, m = NB - r0;
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) {
+                    const int r = tid + 256 * u;
+                    if (r >= r0 && r < NB) {
+#pragma unroll
+                        for (int q = 0; q < 32; ++q) Ls[q * LDL + r] = P[u][q];
+                    }
+                }
+                for (int e = tid; e < 32 * m; e += WG) Ub[(e / 32) * 33 + e % 32] = W[p0 + e % 32 + (r0 + e / 32) * NB];
+                __syncthreads();
+                const int nbk = m / 16;
+                const int gq = l >> 4, i16 = l & 15;
+                for (int blk = w; blk < nbk * nbk; blk += 4) {
+                    const int br = r0 + 16 * (blk % nbk), bc = 16 * (blk / nbk);
+                    d4 acc;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[r] = W[(br + Tr<P64>::drow(gq, r)) + (r0 + bc + i16) * NB];
+#pragma unroll
+                    for (int ks = 0; ks < 8; ++ks)
+                        acc = Tr<P64>::mma(-Ls[(4 * ks + gq) * LDL + br + i16], Ub[(bc + i16) * 33 + 4 * ks + gq], acc);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) W[(br + Tr<P64>::drow(gq, r)) + (r0 + bc + i16) * NB] = acc[r];
                 }
                 __syncthreads();
-                for (int r = p0 + 32 + tid; r < NB; r += WG) {
-                    double lr[32];
+            } else {
+            constexpr int AW = RPT > 1 ? 16 : 32;  // A22 columns per pass (register budget)
+            for (int c0 = p0 + 32; c0 < NB; c0 += AW) {  // A22 -= L21 U12
+                for (int e = tid; e < 32 * AW; e += WG) buf[(e / 32) * 33 + e % 32] = W[p0 + e % 32 + (c0 + e / 32) * NB];
+                __syncthreads();
 #pragma unroll
-                    for (int q = 0; q < 32; ++q) lr[q] = P[q * NB + r];
-                    for (int j = 0; j < 32; ++j) {
-                        double s = W[r + (c0 + j) * NB];
+                for (int u = 0; u < RPT; ++u) {
+                    const int r = tid + 256 * u;
+                    if (r < p0 + 32 || r >= NB) continue;
+                    double wv[AW];
 #pragma unroll
-                        for (int q = 0; q < 32; ++q) s -= lr[q] * Us[j * 33 + q];
-                        W[r + (c0 + j) * NB] = s;
+                    for (int j = 0; j < AW; ++j) wv[j] = W[r + (c0 + j) * NB];
+#pragma unroll
+                    for (int q = 0; q < 32; ++q) {
+                        const double lq = P[u][q];
+#pragma unroll
+                        for (int j = 0; j < AW; ++j) wv[j] -= lq * buf[j * 33 + q];
                     }
+#pragma unroll
+                    for (int j = 0; j < AW; ++j) W[r + (c0 + j) * NB] = wv[j];
                 }
                 __syncthreads();
             }
+            }
         }
+        __syncthreads();
     }
+    // permutation of the whole tile: (P A)(r,:) = A(perm[r],:)
     if (tid == 0) {
-        int *pm = c.perm + (size_t)k * NB;
+        for (int r = 0; r < NB; ++r) src[r] = r;
         const int *ip = c.ipiv + (size_t)k * NB;
-        for (int r = 0; r < NB; ++r) pm[r] = r;
-        for (int cc = 0; cc < NB; ++cc) {
-            int p = ip[cc];
-            int t = pm[cc]; pm[cc] = pm[p]; pm[p] = t;
+        for (int q = 0; q < NB; ++q) {
+            const int p = ip[q];
+            const int t = src[q]; src[q] = src[p]; src[p] = t;
         }
-        c.zpiv[k] = zp;
+        c.zpiv[k] = g.zp;
     }
+    __syncthreads();
+    for (int r = tid; r < NB; r += WG) c.perm[(size_t)k * NB + r] = src[r];
 }
 
 // Column sums and column maxima of |A_ik| (one workgroup per tile).

@@ -1,11 +1,15 @@
 // QR step with TS kernels and a flat reduction tree (Alg. 3 and 4a: the
 // eliminator of every A_ik is A_kk), run only when the device-side decision
 // of step k says QR.  One launch per step:
-//   workgroup 0 (producer): GEQRT(A_kk), then TSQRT(R_kk, A_ik) for
-//     i = k+1..n-1 in order, publishing flag[i] = k+1 after each;
-//   workgroups 1.. (consumers): one 64-column strip of one trailing tile
-//     column j; apply UNMQR to the strip of A_kj once GEQRT is published, then
-//     TSMQR(i) on the strips of (A_kj, A_ij) as each TSQRT(i) is published.
+//   workgroups 0..nb/IB-1 (producers): workgroup b factors column block b
+//     (IB columns) of GEQRT(A_kk) and then of TSQRT(R_kk, A_ik) for
+//     i = k+1..n-1, owning row block b of R_kk throughout.  Unit (i, b) needs
+//     the trailing update of unit (i, b-1) (flag) and R's row block b (its own
+//     previous unit), so the chain advances as a wavefront over (i, b);
+//     flag[i][b] = k+1 publishes the block reflector Y_ib, T_ib;
+//   the other workgroups (consumers): one 64-column strip of one trailing
+//     tile column j; UNMQR on the strip of A_kj, then TSMQR(i) on the strips of
+//     (A_kj, A_ij), block reflector by block reflector as each is published.
 // A consumer keeps both strips in MFMA accumulator registers (each wave owns
 // 16 columns over all nb rows) for the whole chain, so A_kj never leaves the
 // chip between the n-k-1 updates it receives.
@@ -13,273 +17,191 @@
 // when the tail is zero.  Compact-WY factors are kept per IB = 32 columns:
 // block b of T(i,k) sits at rows b*IB.. of the nb x IB tile Tf(i,k).
 #pragma once
+#include <utility>
+
 #include "mma.h"
 
 namespace lq {
 
 template <class S> LQ_DEV S sq(S x) { return x * x; }
 
-// Build the IB x IB compact-WY factor of the panel reflectors from their Gram
-// matrix G(l,q) = v_l^T v_q (l < q): T(q,q) = tau_q,
-// T(0:q,q) = -tau_q T(0:q,0:q) G(0:q,q).  One wave; G, T in LDS [q*IB + l].
+// Sum a 16-vector across the 64 lanes of a wave: stages 0-3 exchange halves
+// of the remaining entries (lane bit 5, 4, 3, 2 choosing the upper half),
+// stages 4-5 add the last partners.  On return lane l holds the total of
+// entry (l >> 2) & 15.
+template <int ST, int H, class S> LQ_DEV void xhalf(S (&v)[16]) {
+    const bool up = (lane_id() >> xbit<ST>()) & 1;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        S send = up ? v[i] : v[i + H];
+        S keep = up ? v[i + H] : v[i];
+        v[i] = keep + xlane<ST>(send);
+    }
+}
 template <class S>
-LQ_DEV void build_t(const S *G, S *Ts, const S *tau) {
-    const int l = lane_id();
-    for (int q = 0; q < IB; ++q) {
-        S v = 0;
-        if (l < q) {
-            for (int p = l; p < q; ++p) v += Ts[p * IB + l] * G[q * IB + p];
-            v = -tau[q] * v;
-        } else if (l == q) {
-            v = tau[q];
-        }
-        if (l < IB) Ts[q * IB + l] = v;
-        wave_sync();
-    }
+LQ_DEV S xreduce16(S (&v)[16]) {
+    xhalf<0, 8>(v);
+    xhalf<1, 4>(v);
+    xhalf<2, 2>(v);
+    xhalf<3, 1>(v);
+    S t = v[0] + xlane<4>(v[0]);
+    return t + xlane<5>(t);
 }
 
+template <int NB> constexpr int qr_rpt() { return NB > 256 ? 2 : 1; }  // panel rows per thread
+
 // ---------------------------------------------------------------------------
-// Producer: GEQRT of A (nb x nb, in place: V below the diagonal, R on and
-// above), T factors into Tt (nb x IB).
+// Producer panel: Householder QR of one IB-column block (c0 = b*IB) with the
+// panel held in registers, thread t owning tile rows t and t+256.
+//   TS = false: GEQRT panel of the tile A (rows c0.., unit-lower V in place).
+//   TS = true:  TSQRT panel of [R; A]: R's diagonal block (Rb, LDS) holds the
+//               pivots, A's whole column is the reflector tail Y.
+// Column q runs as its own instantiation (compile-time q), so every register
+// index is static.  One 32-entry reduction per column yields both the
+// products v_q^T a_j (j > q, the columns still to update) and the Gram
+// entries v_j^T v_q (j < q) that extend the compact-WY factor T.
+// On return Ys holds V (explicit zeros/ones for GEQRT) and Ts holds T.
 // ---------------------------------------------------------------------------
-template <int NB, class S>
-LQ_DEV void geqrt_tile(S *A, S *Tt, char *smem) {
-    constexpr int LD = NB + 1;
-    S *Pn = (S *)smem;          // panel [IB][LD]
-    S *G = Pn + IB * LD;        // [IB*IB]
-    S *Ts = G + IB * IB;        // [IB*IB]
-    S *tau = Ts + IB * IB;      // [IB]
-    S *Wc = tau + IB;           // [IB*33] chunk of W
+struct PanelLds {
+    double red1[4];
+    double red2[32 * 4];  // [j][wave]
+    double alpha;
+};
+
+template <int NB, class S, bool TS, int Q>
+LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *pl) {
+    constexpr int RPT = qr_rpt<NB>();
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
-    for (int c0 = 0; c0 < NB; c0 += IB) {
-        for (int e = tid; e < (NB - c0) * IB; e += WG) {
-            int r = c0 + e % (NB - c0), q = e / (NB - c0);
-            Pn[q * LD + r] = A[r + (c0 + q) * NB];
-        }
-        __syncthreads();
-        if (w == 0) {
-            for (int q = 0; q < IB; ++q) {
-                const int col = c0 + q;
-                S ss = 0;
-                for (int r = col + 1 + l; r < NB; r += 64) ss += sq(Pn[q * LD + r]);
-                ss = wave_sum(ss);
-                const S alpha = Pn[q * LD + col];
-                S t = 0;
-                if (ss != (S)0) {
-                    S nrm = sqrt(alpha * alpha + ss);
-                    S beta = alpha >= (S)0 ? -nrm : nrm;
-                    t = (beta - alpha) / beta;
-                    S scal = (S)1 / (alpha - beta);
-                    for (int r = col + 1 + l; r < NB; r += 64) Pn[q * LD + r] *= scal;
-                    wave_sync();
-                    if (l == 0) Pn[q * LD + col] = beta;
-                }
-                if (l == 0) tau[q] = t;
-                wave_sync();
-                if (t != (S)0) {
-                    for (int j = q + 1; j < IB; ++j) {
-                        S d = 0;
-                        for (int r = col + 1 + l; r < NB; r += 64) d += Pn[q * LD + r] * Pn[j * LD + r];
-                        d = wave_sum(d);
-                        const S wv = t * (Pn[j * LD + col] + d);
-                        for (int r = col + 1 + l; r < NB; r += 64) Pn[j * LD + r] -= Pn[q * LD + r] * wv;
-                        wave_sync();
-                        if (l == 0) Pn[j * LD + col] -= wv;
-                        wave_sync();
-                    }
-                }
+    const int pr = c0 + Q;  // GEQRT pivot row
+    S ss = 0;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int r = tid + 256 * u;
+        if (TS ? r < NB : (r > pr && r < NB)) ss += sq(P[u][Q]);
+        if (!TS && r == pr) pl->alpha = (double)P[u][Q];
+    }
+    ss = wave_sum(ss);
+    if (l == 0) pl->red1[w] = (double)ss;
+    __syncthreads();  // A: norms and the pivot are visible
+    ss = (S)((pl->red1[0] + pl->red1[1]) + (pl->red1[2] + pl->red1[3]));
+    const S alpha = TS ? Rb[Q * IB + Q] : (S)pl->alpha;
+    S rq[IB];  // TS: row Q of R's diagonal block, issued early to overlap the scalar work
+#pragma unroll
+    for (int j = 0; j < IB; ++j) rq[j] = (TS && j > Q) ? Rb[j * IB + Q] : (S)0;
+    S tau = 0, beta = alpha, scal = 1;
+    if (ss != (S)0) {
+        const S nrm = sqrt(alpha * alpha + ss);
+        beta = alpha >= (S)0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = (S)1 / (alpha - beta);
+    }
+    S vq[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int r = tid + 256 * u;
+        S v;
+        if (TS) v = r < NB ? P[u][Q] * scal : (S)0;
+        else v = (r == pr) ? (S)1 : ((r > pr && r < NB) ? P[u][Q] * scal : (S)0);
+        vq[u] = v;
+        if (TS ? r < NB : (r > pr && r < NB)) P[u][Q] = v;
+        if (!TS && r == pr) P[u][Q] = beta;
+    }
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        S part[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = 16 * half + jj;
+            S acc = 0;
+            if (j != Q) {
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) acc += vq[u] * P[u][j];
+                // TS: the pivot row of v_q lives in R (entry 1 at row q): add R(q, j) once
+                if (TS && j > Q && tid == 0) acc += rq[j];
             }
+            part[jj] = acc;
         }
-        __syncthreads();
-        // Gram matrix of the block's reflectors: v_l = e_{c0+l} + tail below row c0+l
-        for (int e = tid; e < IB * IB; e += WG) {
-            int lq = e % IB, q = e / IB;
-            S g = 0;
-            if (lq < q) {
-                g = Pn[lq * LD + c0 + q];
-                for (int r = c0 + q + 1; r < NB; ++r) g += Pn[lq * LD + r] * Pn[q * LD + r];
-            }
-            G[q * IB + lq] = g;
+        const S tot = xreduce16<S>(part);
+        if ((l & 3) == 0) pl->red2[(16 * half + (l >> 2)) * 4 + w] = (double)tot;
+    }
+    __syncthreads();  // B: all partial products visible; alpha and R row q read
+    S d[IB];  // reduced products: all LDS reads issued before any use
+#pragma unroll
+    for (int j = 0; j < IB; ++j) {
+        if (j == Q) { d[j] = 0; continue; }
+        const double *rj = &pl->red2[j * 4];
+        d[j] = (S)((rj[0] + rj[1]) + (rj[2] + rj[3]));
+    }
+    if (tau != (S)0) {
+#pragma unroll
+        for (int j = Q + 1; j < IB; ++j) {
+            const S wj = tau * d[j];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) P[u][j] -= vq[u] * wj;
+            if (TS && tid == j) Rb[j * IB + Q] = rq[j] - wj;
         }
-        __syncthreads();
-        if (w == 0) build_t<S>(G, Ts, tau);
-        __syncthreads();
-        for (int e = tid; e < (NB - c0) * IB; e += WG) {
-            int r = c0 + e % (NB - c0), q = e / (NB - c0);
-            A[r + (c0 + q) * NB] = Pn[q * LD + r];
-        }
-        for (int e = tid; e < IB * IB; e += WG) {
-            int p = e % IB, q = e / IB;
-            Tt[(c0 + p) + q * NB] = Ts[q * IB + p];
-        }
-        // trailing columns: C <- (I - V T V^T)^T C, 32 columns at a time
-        for (int j0 = c0 + IB; j0 < NB; j0 += 32) {
-            __syncthreads();
-            for (int e = tid; e < IB * 32; e += WG) {  // Wc = V^T C
-                int lq = e % IB, jj = e / IB;
-                const S *Cc = A + (j0 + jj) * NB;
-                S s = Cc[c0 + lq];
-                for (int r = c0 + lq + 1; r < NB; ++r) s += Pn[lq * LD + r] * Cc[r];
-                Wc[jj * 33 + lq] = s;
-            }
-            __syncthreads();
-            S w2[4];
-            for (int u = 0; u < 4; ++u) {  // W2 = T^T Wc
-                int e = tid + u * WG;
-                int lq = e % IB, jj = e / IB;
-                S s = 0;
-                for (int p = 0; p <= lq; ++p) s += Ts[lq * IB + p] * Wc[jj * 33 + p];
-                w2[u] = s;
-            }
-            __syncthreads();
-            for (int u = 0; u < 4; ++u) {
-                int e = tid + u * WG;
-                Wc[(e / IB) * 33 + e % IB] = w2[u];
-            }
-            __syncthreads();
-            for (int e = tid; e < (NB - c0) * 32; e += WG) {  // C -= V W2
-                int r = c0 + e % (NB - c0), jj = e / (NB - c0);
-                S s = 0;
-                const int lmax = r - c0 < IB ? r - c0 : IB - 1;
-                for (int lq = 0; lq <= lmax; ++lq) {
-                    S v = (r == c0 + lq) ? (S)1 : Pn[lq * LD + r];
-                    s += v * Wc[jj * 33 + lq];
-                }
-                A[r + (j0 + jj) * NB] -= s;
-            }
-        }
-        __syncthreads();
+    }
+    if (TS && tid == 0) Rb[Q * IB + Q] = beta;
+    // T(0:q, q) = -tau T(0:q, 0:q) G(0:q, q), with G(p, q) = v_p^T v_q = d[p]
+    if (tid < Q) {
+        S acc = 0;
+#pragma unroll
+        for (int p = 0; p < Q; ++p)
+            if (p >= tid) acc += Ts[p * IB + tid] * d[p];
+        Ts[Q * IB + tid] = -tau * acc;
+    } else if (tid < IB) {
+        Ts[Q * IB + tid] = tid == Q ? tau : (S)0;
     }
 }
 
-// ---------------------------------------------------------------------------
-// Producer: TSQRT of [R; A] (R = upper triangle of the nb x nb tile Rt,
-// A = nb x nb tile): Y overwrites A, R is updated in place, T into Tt.
-// ---------------------------------------------------------------------------
-template <int NB, class S>
-LQ_DEV void tsqrt_tile(S *Rt, S *A, S *Tt, char *smem) {
-    constexpr int LD = NB + 1;
-    S *Pn = (S *)smem;           // [IB][LD]
-    S *G = Pn + IB * LD;
-    S *Ts = G + IB * IB;
-    S *tau = Ts + IB * IB;
-    S *Wc = tau + IB;            // [32*33]
-    S *Rb = Wc + 32 * 33;        // [IB*IB] diagonal block of R, Rb[q*IB + p] = R(c0+p, c0+q)
-    const int tid = threadIdx.x, l = lane_id(), w = wave_id();
-    for (int c0 = 0; c0 < NB; c0 += IB) {
-        for (int e = tid; e < NB * IB; e += WG) {
-            int r = e % NB, q = e / NB;
-            Pn[q * LD + r] = A[r + (c0 + q) * NB];
-        }
-        for (int e = tid; e < IB * IB; e += WG) {
-            int p = e % IB, q = e / IB;
-            Rb[q * IB + p] = p <= q ? Rt[(c0 + p) + (c0 + q) * NB] : (S)0;
-        }
-        __syncthreads();
-        if (w == 0) {
-            for (int q = 0; q < IB; ++q) {
-                S ss = 0;
-                for (int r = l; r < NB; r += 64) ss += sq(Pn[q * LD + r]);
-                ss = wave_sum(ss);
-                const S alpha = Rb[q * IB + q];
-                S t = 0;
-                if (ss != (S)0) {
-                    S nrm = sqrt(alpha * alpha + ss);
-                    S beta = alpha >= (S)0 ? -nrm : nrm;
-                    t = (beta - alpha) / beta;
-                    S scal = (S)1 / (alpha - beta);
-                    for (int r = l; r < NB; r += 64) Pn[q * LD + r] *= scal;
-                    wave_sync();
-                    if (l == 0) Rb[q * IB + q] = beta;
-                }
-                if (l == 0) tau[q] = t;
-                wave_sync();
-                if (t != (S)0) {
-                    for (int j = q + 1; j < IB; ++j) {
-                        S d = 0;
-                        for (int r = l; r < NB; r += 64) d += Pn[q * LD + r] * Pn[j * LD + r];
-                        d = wave_sum(d);
-                        const S wv = t * (Rb[j * IB + q] + d);
-                        for (int r = l; r < NB; r += 64) Pn[j * LD + r] -= Pn[q * LD + r] * wv;
-                        wave_sync();
-                        if (l == 0) Rb[j * IB + q] -= wv;
-                        wave_sync();
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < IB * IB; e += WG) {  // Gram of the Y parts (the e_c parts are orthonormal)
-            int lq = e % IB, q = e / IB;
-            S g = 0;
-            if (lq < q)
-                for (int r = 0; r < NB; ++r) g += Pn[lq * LD + r] * Pn[q * LD + r];
-            G[q * IB + lq] = g;
-        }
-        __syncthreads();
-        if (w == 0) build_t<S>(G, Ts, tau);
-        __syncthreads();
-        for (int e = tid; e < NB * IB; e += WG) {
-            int r = e % NB, q = e / NB;
-            A[r + (c0 + q) * NB] = Pn[q * LD + r];
-        }
-        for (int e = tid; e < IB * IB; e += WG) {
-            int p = e % IB, q = e / IB;
-            if (p <= q) Rt[(c0 + p) + (c0 + q) * NB] = Rb[q * IB + p];
-            Tt[(c0 + p) + q * NB] = Ts[q * IB + p];
-        }
-        for (int j0 = c0 + IB; j0 < NB; j0 += 32) {
-            __syncthreads();
-            for (int e = tid; e < IB * 32; e += WG) {  // Wc = R(c0.., cols) + Y^T A(:, cols)
-                int lq = e % IB, jj = e / IB;
-                const S *Cc = A + (j0 + jj) * NB;
-                S s = Rt[(c0 + lq) + (j0 + jj) * NB];
-                for (int r = 0; r < NB; ++r) s += Pn[lq * LD + r] * Cc[r];
-                Wc[jj * 33 + lq] = s;
-            }
-            __syncthreads();
-            S w2[4];
-            for (int u = 0; u < 4; ++u) {
-                int e = tid + u * WG;
-                int lq = e % IB, jj = e / IB;
-                S s = 0;
-                for (int p = 0; p <= lq; ++p) s += Ts[lq * IB + p] * Wc[jj * 33 + p];
-                w2[u] = s;
-            }
-            __syncthreads();
-            for (int u = 0; u < 4; ++u) {
-                int e = tid + u * WG;
-                int lq = e % IB, jj = e / IB;
-                Wc[jj * 33 + lq] = w2[u];
-                Rt[(c0 + lq) + (j0 + jj) * NB] -= w2[u];
-            }
-            __syncthreads();
-            for (int e = tid; e < NB * 32; e += WG) {
-                int r = e % NB, jj = e / NB;
-                S s = 0;
-#pragma unroll 8
-                for (int lq = 0; lq < IB; ++lq) s += Pn[lq * LD + r] * Wc[jj * 33 + lq];
-                A[r + (j0 + jj) * NB] -= s;
-            }
-        }
-        __syncthreads();
-    }
+template <int NB, class S, bool TS, int... Qs>
+LQ_DEV void qr_columns(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *pl,
+                       std::integer_sequence<int, Qs...>) {
+    (qr_column<NB, S, TS, Qs>(P, c0, Rb, Ts, pl), ...);
 }
 
-template <int NB, class S> constexpr int producer_lds() {
-    return (IB * (NB + 1) + 3 * IB * IB + IB + 32 * 33) * (int)sizeof(S);
+template <int NB, class S, bool TS>
+LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
+    constexpr int RPT = qr_rpt<NB>();
+    constexpr int LDY = NB + 1;
+    const int tid = threadIdx.x;
+    S P[RPT][IB];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int r = tid + 256 * u;
+#pragma unroll
+        for (int q = 0; q < IB; ++q)
+            P[u][q] = (r < NB && (TS || r >= c0)) ? A[r + (c0 + q) * NB] : (S)0;
+    }
+    qr_columns<NB, S, TS>(P, c0, Rb, Ts, pl, std::make_integer_sequence<int, IB>{});
+    // write the panel back and expose V to the trailing update
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int r = tid + 256 * u;
+        if (r >= NB) continue;
+#pragma unroll
+        for (int q = 0; q < IB; ++q) {
+            if (TS || r >= c0) A[r + (c0 + q) * NB] = P[u][q];
+            S v;
+            if (TS) v = P[u][q];
+            else v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : P[u][q]);
+            Ys[q * LDY + r] = v;
+        }
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Consumer: apply one block reflector (I - V T V^T)^T to a wave's 16-column
-// slice.  `bot` holds all nb rows of the slice being eliminated into; when
-// HAS_TOP, `top` holds the eliminator row tile and only its rows
-// [c0, c0+IB) take part (TS structure: V = [E; Y]).  Without HAS_TOP the
-// reflector lives entirely in `bot`'s rows (UNMQR; V given explicitly).
-// Ys[q*LDY + r] = Y(r, q), Ts[q*IB + p] = T(p, q).
+// slice.  `bot` holds all nb rows of the slice being eliminated into, in MFMA
+// accumulator layout; when HAS_TOP, `top` points at the eliminator row tile's
+// column for this lane (element of row r at top[r]) and only its rows
+// [c0, c0+IB) take part (TS structure: V = [E; Y]); they are read and written
+// in place.  Without HAS_TOP the reflector lives entirely in `bot`'s rows
+// (UNMQR; V given explicitly).  Ys[q*LDY + r] = Y(r, q), Ts[q*IB + p] = T(p, q).
 // ---------------------------------------------------------------------------
 template <int NB, int P, bool HAS_TOP>
-LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::acc (&top)[NB / 16], int b,
+LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *top, int b,
                         const typename Tr<P>::S *Ys, const typename Tr<P>::S *Ts) {
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
@@ -287,8 +209,15 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::acc
     constexpr int P2 = (P == P64) ? P64 : P32;  // precision of the small T^T W product
     const int l = lane_id(), g = l >> 4, i16 = l & 15;
     acc_t Wb[2];
-    if constexpr (HAS_TOP) { Wb[0] = top[2 * b]; Wb[1] = top[2 * b + 1]; }
-    else { Wb[0] = zero_acc<acc_t>(); Wb[1] = zero_acc<acc_t>(); }
+    if constexpr (HAS_TOP) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Wb[h][r] = top[32 * b + 16 * h + Tr<P>::drow(g, r)];
+    } else {
+        Wb[0] = zero_acc<acc_t>();
+        Wb[1] = zero_acc<acc_t>();
+    }
     // W += Y^T bot
     if constexpr (P != PB16) {
 #pragma unroll
@@ -310,7 +239,8 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::acc
             for (int qb = 0; qb < 2; ++qb) {
                 bf8 a;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) a[e] = (__bf16)Ys[(16 * qb + i16) * LDY + 32 * pr + 16 * (e >> 2) + Tr<P>::drow(g, e & 3)];
+                for (int e = 0; e < 8; ++e)
+                    a[e] = (__bf16)Ys[(16 * qb + i16) * LDY + 32 * pr + 16 * (e >> 2) + Tr<P>::drow(g, e & 3)];
                 Wb[qb] = Tr<PB16>::mma(a, bo, Wb[qb]);
             }
         }
@@ -325,8 +255,13 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::acc
             for (int ob = 0; ob < 2; ++ob)
                 Wp[ob] = Tr<P2>::mma(Ts[(16 * ob + i16) * IB + 16 * qb + Tr<P>::drow(g, r)], Wb[qb][r], Wp[ob]);
     if constexpr (HAS_TOP) {
-        top[2 * b] -= Wp[0];
-        top[2 * b + 1] -= Wp[1];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                S *t = &top[32 * b + 16 * h + Tr<P>::drow(g, r)];
+                *t = (S)(*t - Wp[h][r]);
+            }
     }
     // bot -= Y W'
     if constexpr (P != PB16) {
@@ -345,23 +280,103 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::acc
         for (int rb = 0; rb < NB / 16; ++rb) {
             bf8 a;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) a[e] = (__bf16)(-Ys[(16 * (e >> 2) + Tr<P>::drow(g, e & 3)) * LDY + 16 * rb + i16]);
+            for (int e = 0; e < 8; ++e)
+                a[e] = (__bf16)(-Ys[(16 * (e >> 2) + Tr<P>::drow(g, e & 3)) * LDY + 16 * rb + i16]);
             bot[rb] = Tr<PB16>::mma(a, bw, bot[rb]);
         }
     }
 }
 
-template <int NB, int P> constexpr int consumer_lds() {
-    return (IB * (NB + 1) + IB * IB) * (int)sizeof(typename Tr<P>::S);
+// Trailing update of a producer panel: columns (b+1)*IB..NB-1 of A (and, for
+// TS, rows b*IB..b*IB+IB of R) in 64-column strips, with the consumer routine.
+template <int NB, int P, bool TS>
+LQ_DEV void panel_trailing(typename Tr<P>::S *A, typename Tr<P>::S *R, int b, const typename Tr<P>::S *Ys,
+                           const typename Tr<P>::S *Ts) {
+    typedef typename Tr<P>::S S;
+    typedef typename Tr<P>::acc acc_t;
+    const int l = lane_id(), w = wave_id(), g = l >> 4, i16 = l & 15;
+    for (int s0 = (b + 1) * IB; s0 < NB; s0 += 64) {
+        const int col = s0 + 16 * w;
+        if (col >= NB) continue;
+        acc_t bot[NB / 16];
+#pragma unroll
+        for (int rb = 0; rb < NB / 16; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bot[rb][r] = A[(16 * rb + Tr<P>::drow(g, r)) + (col + i16) * NB];
+        apply_block<NB, P, TS>(bot, TS ? R + (col + i16) * NB : nullptr, b, Ys, Ts);
+        // GEQRT: rows above the block are untouched by its reflectors and belong
+        // to R row blocks other producers are updating: write back rows >= c0 only
+#pragma unroll
+        for (int rb = 0; rb < NB / 16; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rb + Tr<P>::drow(g, r);
+                if (TS || row >= b * IB) A[row + (col + i16) * NB] = (S)bot[rb][r];
+            }
+    }
 }
 
 template <int NB, int P> constexpr int qr_lds() {
-    return producer_lds<NB, typename Tr<P>::S>() > consumer_lds<NB, P>() ? producer_lds<NB, typename Tr<P>::S>()
-                                                                        : consumer_lds<NB, P>();
+    return (IB * (NB + 1) + 2 * IB * IB) * (int)sizeof(typename Tr<P>::S) + (int)sizeof(PanelLds);
 }
 
 // Strips of 64 columns (16 per wave); for nb = 32 one strip with two active waves.
 template <int NB> constexpr int qr_spc() { return NB >= 64 ? NB / 64 : 1; }
+
+template <int NB> constexpr int qr_pw() { return NB / IB; }  // producer workgroups
+
+LQ_DEV int *qr_flag(const Ctx &c, int i, int b) { return &c.flags[(size_t)i * (c.nb / IB) + b]; }
+
+// Producer workgroup b of one QR step: block b of GEQRT(A_kk), then block b
+// of each TSQRT(A_kk, A_ik) in order of i.
+template <int NB, int P>
+LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
+    typedef typename Tr<P>::S S;
+    constexpr int PP = (P == PB16) ? P32 : P;  // panel-internal updates stay in the storage precision
+    constexpr int LDY = NB + 1;
+    S *Ys = (S *)smem;
+    S *Ts = Ys + IB * LDY;
+    S *Rb = Ts + IB * IB;
+    PanelLds *pl = (PanelLds *)(Rb + IB * IB);
+    __shared__ int bail;
+    S *At = (S *)c.At;
+    S *Tf = (S *)c.Tf;
+    const int tid = threadIdx.x;
+    const int epoch = k + 1;
+    const int c0 = b * IB;
+    S *Akk = At + c.toff(k, k);
+    for (int i = k; i < c.n; ++i) {
+        if (b > 0) {  // the trailing update of unit (i, b-1) must be in place
+            if (tid == 0) bail = !flag_wait(qr_flag(c, i, b - 1), epoch, &c.st->watchdog);
+            __syncthreads();
+            if (bail) return;
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        }
+        S *Ti = Tf + c.toff(i, k) / NB * IB;
+        if (i == k) {
+            panel_qr<NB, S, false>(Akk, c0, nullptr, Ys, Ts, pl);
+            for (int e = tid; e < IB * IB; e += WG) Ti[(c0 + e % IB) + (e / IB) * NB] = Ts[e];
+            panel_trailing<NB, PP, false>(Akk, nullptr, b, Ys, Ts);
+        } else {
+            S *Aik = At + c.toff(i, k);
+            for (int e = tid; e < IB * IB; e += WG) {
+                const int p = e % IB, q = e / IB;
+                Rb[e] = p <= q ? Akk[(c0 + p) + (c0 + q) * NB] : (S)0;
+            }
+            __syncthreads();
+            panel_qr<NB, S, true>(Aik, c0, Rb, Ys, Ts, pl);
+            for (int e = tid; e < IB * IB; e += WG) {
+                const int p = e % IB, q = e / IB;
+                if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[e];
+                Ti[(c0 + p) + q * NB] = Ts[e];
+            }
+            panel_trailing<NB, PP, true>(Aik, Akk, b, Ys, Ts);
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) flag_publish(qr_flag(c, i, b), epoch);
+    }
+}
 
 template <int NB, int P>
 __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
@@ -370,49 +385,40 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
     typedef typename Tr<P>::acc acc_t;
     constexpr int LDY = NB + 1;
     __shared__ __attribute__((aligned(16))) char smem[qr_lds<NB, P>()];
+    if ((int)blockIdx.x < qr_pw<NB>()) {
+        qr_producer<NB, P>(c, k, (int)blockIdx.x, smem);
+        return;
+    }
     S *At = (S *)c.At;
     S *Tf = (S *)c.Tf;
     const int epoch = k + 1;
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
-    if (blockIdx.x == 0) {
-        S *Akk = At + c.toff(k, k);
-        geqrt_tile<NB, S>(Akk, Tf + c.toff(k, k) / NB * IB, smem);
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) flag_publish(&c.flags[k], epoch);
-        for (int i = k + 1; i < c.n; ++i) {
-            tsqrt_tile<NB, S>(Akk, At + c.toff(i, k), Tf + c.toff(i, k) / NB * IB, smem);
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) flag_publish(&c.flags[i], epoch);
-        }
-        return;
-    }
-    const int strip = (int)blockIdx.x - 1;
+    const int strip = (int)blockIdx.x - qr_pw<NB>();
     const int j = k + 1 + strip / qr_spc<NB>();
     const int col0 = (strip % qr_spc<NB>()) * 64 + 16 * w;
     const bool active = col0 < NB;
     S *Ys = (S *)smem;
     S *Ts = Ys + IB * LDY;
-    acc_t top[NB / 16], bot[NB / 16];
+    acc_t bot[NB / 16];
     S *Akj = At + c.toff(k, j);
+    S *topc = Akj + (col0 + (l & 15)) * NB;  // this lane's column of the eliminator row tile
     const int g = l >> 4, i16 = l & 15;
-    if (active) {
-#pragma unroll
-        for (int rb = 0; rb < NB / 16; ++rb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) top[rb][r] = Akj[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB];
-    }
     __shared__ int bail;
-    if (tid == 0) bail = !flag_wait(&c.flags[k], epoch, &c.st->watchdog);
-    __syncthreads();
-    if (bail) return;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
     {  // UNMQR on the strip of A_kj: explicit V blocks of the GEQRT tile
         const S *V = At + c.toff(k, k);
         const S *T = Tf + c.toff(k, k) / NB * IB;
+        if (active) {
+#pragma unroll
+            for (int rb = 0; rb < NB / 16; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) bot[rb][r] = Akj[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB];
+        }
         for (int b = 0; b < NB / IB; ++b) {
             const int c0 = b * IB;
+            if (tid == 0) bail = !flag_wait(qr_flag(c, k, b), epoch, &c.st->watchdog);
+            __syncthreads();
+            if (bail) return;
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
             for (int e = tid; e < NB * IB; e += WG) {
                 int r = e % NB, q = e / NB;
                 S v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : V[r + (c0 + q) * NB]);
@@ -420,15 +426,17 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
             }
             for (int e = tid; e < IB * IB; e += WG) Ts[(e / IB) * IB + e % IB] = T[(c0 + e % IB) + (e / IB) * NB];
             __syncthreads();
-            if (active) apply_block<NB, P, false>(top, bot, b, Ys, Ts);
+            if (active) apply_block<NB, P, false>(bot, nullptr, b, Ys, Ts);
             __syncthreads();
+        }
+        if (active) {
+#pragma unroll
+            for (int rb = 0; rb < NB / 16; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Akj[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB] = (S)bot[rb][r];
         }
     }
     for (int i = k + 1; i < c.n; ++i) {
-        if (tid == 0) bail = !flag_wait(&c.flags[i], epoch, &c.st->watchdog);
-        __syncthreads();
-        if (bail) return;
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
         S *Aij = At + c.toff(i, j);
         const S *Y = At + c.toff(i, k);
         const S *T = Tf + c.toff(i, k) / NB * IB;
@@ -440,13 +448,17 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
         }
         for (int b = 0; b < NB / IB; ++b) {
             const int c0 = b * IB;
+            if (tid == 0) bail = !flag_wait(qr_flag(c, i, b), epoch, &c.st->watchdog);
+            __syncthreads();
+            if (bail) return;
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
             for (int e = tid; e < NB * IB; e += WG) {
                 int r = e % NB, q = e / NB;
                 Ys[q * LDY + r] = Y[r + (c0 + q) * NB];
             }
             for (int e = tid; e < IB * IB; e += WG) Ts[(e / IB) * IB + e % IB] = T[(c0 + e % IB) + (e / IB) * NB];
             __syncthreads();
-            if (active) apply_block<NB, P, true>(bot, top, b, Ys, Ts);
+            if (active) apply_block<NB, P, true>(bot, topc, b, Ys, Ts);
             __syncthreads();
         }
         if (active) {
@@ -455,12 +467,6 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Aij[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB] = (S)bot[rb][r];
         }
-    }
-    if (active) {
-#pragma unroll
-        for (int rb = 0; rb < NB / 16; ++rb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Akj[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB] = (S)top[rb][r];
     }
 }
 

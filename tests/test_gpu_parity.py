@@ -79,6 +79,8 @@ CASES = [
     ("gaussian", 1024, 128, "max", 1.0),        # the FP64 N=1024, nb=128 configuration
     ("diag_dominant", 1000, 128, "max", 4.0),
     ("gaussian", 512, 256, "max", 3000.0),
+    ("gaussian", 2048, 256, "max", 0.0),        # 8 producer workgroups in flight per QR step
+    ("gaussian", 2048, 256, "max", 30000.0),    # hybrid sequence at nb = 256
 ]
 
 
