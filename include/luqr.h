@@ -71,6 +71,9 @@ typedef struct {
     int32_t nsteps;      /* run only the first nsteps panel steps (< 0: all); a partial
                             factorization cannot be solved with */
     int32_t mumps_reading; /* 0 (default): estimate_max(j) = away_max(j) * prod_{i<j} growth(i) */
+    int32_t timing;      /* nonzero: record HIP events around each step's panel, LU-branch and
+                            QR-branch kernels (read back with luqr_get_step_times) */
+    int32_t reserved;
 } luqr_opts;
 
 /* Device-side numerical status, read back by luqr_get_status. */
@@ -126,6 +129,15 @@ int luqr_get_decisions(luqr_factors f, int8_t *dec, double *s, double *m, double
 
 /* Read the device status (waits for the handle's stream). */
 int luqr_get_status(luqr_factors f, luqr_status *st);
+
+/* Per-step kernel durations in milliseconds, from the HIP events recorded on
+ * the factorization stream when opts.timing was set: panel[k] (GETRF copy,
+ * tile norms, triangular inverses, inverse norm, decision), lu[k] (the LU
+ * branch kernels) and qr[k] (the QR branch kernels), k < n.  A branch that the
+ * decision skipped still appears with the few microseconds its early-exit
+ * launch takes.  Arrays may be NULL.  Waits for the stream.  Returns
+ * LUQR_ERR_UNSUPPORTED if the handle was created without timing. */
+int luqr_get_step_times(luqr_factors f, float *panel, float *lu, float *qr, int64_t n);
 
 /* Copy the factored matrix to dF (device, FP64, N x N, column-major, ldf) in
  * the layout the paper describes in-place (L\U or V\R on the diagonal tiles,

@@ -17,14 +17,15 @@ CRITERIA = {"max": 0, "sum": 1, "mumps": 2, "random": 3, "forced": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["luqr_workspace_bytes", "luqr_factor", "luqr_solve", "luqr_solve_refined",
-            "luqr_get_decisions", "luqr_get_status", "luqr_export_factors", "luqr_destroy",
+            "luqr_get_decisions", "luqr_get_status", "luqr_get_step_times", "luqr_export_factors", "luqr_destroy",
             "luqr_batched_workspace_bytes", "luqr_batched_solve"]
 
 
 class luqr_opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("criterion", C.c_int32), ("alpha", C.c_double),
                 ("precision", C.c_int32), ("nrhs_max", C.c_int32), ("seed", C.c_uint64),
-                ("forced", C.POINTER(C.c_int8)), ("nsteps", C.c_int32), ("mumps_reading", C.c_int32)]
+                ("forced", C.POINTER(C.c_int8)), ("nsteps", C.c_int32), ("mumps_reading", C.c_int32),
+                ("timing", C.c_int32), ("reserved", C.c_int32)]
 
 
 class luqr_status(C.Structure):
@@ -72,6 +73,8 @@ def lib() -> C.CDLL:
     L.luqr_get_decisions.argtypes = [vp, vp, vp, vp, vp, i64]
     L.luqr_get_status.restype = C.c_int
     L.luqr_get_status.argtypes = [vp, C.POINTER(luqr_status)]
+    L.luqr_get_step_times.restype = C.c_int
+    L.luqr_get_step_times.argtypes = [vp, vp, vp, vp, i64]
     L.luqr_export_factors.restype = C.c_int
     L.luqr_export_factors.argtypes = [vp, vp, i64, vp, vp]
     L.luqr_destroy.restype = None
@@ -85,7 +88,7 @@ def lib() -> C.CDLL:
 
 
 def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed=0, forced=None,
-              nsteps=-1, mumps_reading=0):
+              nsteps=-1, mumps_reading=0, timing=False):
     o = luqr_opts()
     o.nb = int(nb)
     o.criterion = CRITERIA[criterion] if isinstance(criterion, str) else int(criterion)
@@ -99,6 +102,7 @@ def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed
         o.forced = C.cast(keep, C.POINTER(C.c_int8))
     o.nsteps = int(nsteps)
     o.mumps_reading = int(mumps_reading)
+    o.timing = 1 if timing else 0
     return o, keep
 
 
@@ -131,6 +135,10 @@ def luqr_get_status(h):
     st = luqr_status()
     check(lib().luqr_get_status(h, C.byref(st)), "luqr_get_status")
     return st
+
+
+def luqr_get_step_times(h, panel, lu, qr, n):
+    return check(lib().luqr_get_step_times(h, panel, lu, qr, n), "luqr_get_step_times")
 
 
 def luqr_export_factors(h, dF, ldf, ipiv, stream):

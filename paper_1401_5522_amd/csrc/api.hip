@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "engine.h"
 
@@ -16,6 +17,7 @@ struct luqr_factors_s {
     hipStream_t stream;
     luqr_opts o;
     int nsteps;
+    std::vector<hipEvent_t> ev;  // 4 per step when opts.timing is set
 };
 
 static const Ops *pick_ops(int nb, int prec) {
@@ -73,10 +75,17 @@ extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_
     f->o = *o;
     f->o.forced = nullptr;
     f->nsteps = (o->nsteps < 0 || o->nsteps > L.n) ? (int)L.n : o->nsteps;
+    if (o->timing) {
+        f->ev.resize((size_t)4 * f->nsteps);
+        for (auto &e : f->ev) {
+            hipError_t he = hipEventCreate(&e);
+            if (he != hipSuccess) { e = nullptr; luqr_destroy(f); return hip_rc(he); }
+        }
+    }
     (void)hipGetLastError();
-    f->ops->factor(f->c, L, dA, lda, *o, f->nsteps, f->stream);
+    f->ops->factor(f->c, L, dA, lda, *o, f->nsteps, f->stream, f->ev.empty() ? nullptr : f->ev.data());
     rc = hip_rc(hipGetLastError());
-    if (rc) { delete f; return rc; }
+    if (rc) { luqr_destroy(f); return rc; }
     *out = f;
     return 0;
 }
@@ -138,7 +147,8 @@ extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda,
     SolveArgs s = solve_args(f, nq, nullptr);
     k_rhs_in<<<nblk(total), WG, 0, st>>>(dB, ldb, s.Y, L.N, L.Np, nq, nullptr);
     f->ops->solve(f->c, L, s, st);
-    hipMemcpyAsync(Xk, s.X, total * sizeof(double), hipMemcpyDeviceToDevice, st);
+    hipError_t ce = hipMemcpyAsync(Xk, s.X, total * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (ce != hipSuccess) return hip_rc(ce);
     const dim3 rgrid(nblk(L.N), (unsigned)L.nparts, (unsigned)((nq + RQR - 1) / RQR));
     const dim3 rgrid_final(nblk(L.N * nrhs));
     for (int it = 0; it <= max_iter; ++it) {
@@ -230,7 +240,28 @@ extern "C" int luqr_export_factors(luqr_factors f, double *dF, int64_t ldf, int3
     return 0;
 }
 
-extern "C" void luqr_destroy(luqr_factors f) { delete f; }
+extern "C" int luqr_get_step_times(luqr_factors f, float *panel, float *lu, float *qr, int64_t n) {
+    if (!f) return -1;
+    if (n < 0 || n > f->nsteps) return -5;
+    if (f->ev.empty()) return LUQR_ERR_UNSUPPORTED;
+    hipError_t e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_rc(e);
+    for (int64_t k = 0; k < n; ++k) {
+        hipEvent_t *v = &f->ev[4 * k];
+        float t;
+        if (panel) { if ((e = hipEventElapsedTime(&t, v[0], v[1])) != hipSuccess) return hip_rc(e); panel[k] = t; }
+        if (lu) { if ((e = hipEventElapsedTime(&t, v[1], v[2])) != hipSuccess) return hip_rc(e); lu[k] = t; }
+        if (qr) { if ((e = hipEventElapsedTime(&t, v[2], v[3])) != hipSuccess) return hip_rc(e); qr[k] = t; }
+    }
+    return 0;
+}
+
+extern "C" void luqr_destroy(luqr_factors f) {
+    if (!f) return;
+    for (auto &e : f->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete f;
+}
 
 extern "C" int64_t luqr_batched_workspace_bytes(int64_t batch, const int64_t *N, int64_t nrhs, const luqr_opts *o) {
     (void)batch; (void)N; (void)nrhs; (void)o;

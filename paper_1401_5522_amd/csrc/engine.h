@@ -13,7 +13,7 @@ namespace lq {
 
 struct Ops {
     void (*factor)(const Ctx &, const Layout &, const double *A, int64_t lda, const luqr_opts &, int nsteps,
-                   hipStream_t);
+                   hipStream_t, hipEvent_t *ev);
     void (*solve)(const Ctx &, const Layout &, SolveArgs, hipStream_t);
     void (*export_factors)(const Ctx &, const Layout &, double *F, int64_t ldf, hipStream_t);
 };
@@ -24,8 +24,10 @@ template <int NB, int P>
 struct Eng {
     typedef typename Tr<P>::S S;
 
+    // ev (optional): 4 events per step, recorded before the panel kernels, the
+    // LU-branch kernels, the QR-branch kernels and after the last of them.
     static void factor(const Ctx &c, const Layout &L, const double *A, int64_t lda, const luqr_opts &o, int nsteps,
-                       hipStream_t st) {
+                       hipStream_t st, hipEvent_t *ev) {
         const int n = (int)c.n;
         k_status_reset<<<1, 64, 0, st>>>(c.st);
         k_fill_int<<<nblk((int64_t)n * (NB / IB)), WG, 0, st>>>(c.flags, (int64_t)n * (NB / IB), 0);
@@ -35,6 +37,7 @@ struct Eng {
         constexpr int B = NB < 64 ? NB : 64;
         for (int k = 0; k < nsteps; ++k) {
             const int rest = n - k - 1;
+            if (ev) (void)hipEventRecord(ev[4 * k + 0], st);
             k_panel_a<NB, S><<<n - k, WG, 0, st>>>(c, k);
             k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
             k_panel_invnorm<NB><<<(NB / B) * (NB / B), WG, 0, st>>>(c, k);
@@ -45,13 +48,16 @@ struct Eng {
             a.seed = o.seed;
             a.mumps_reading = o.mumps_reading;
             k_panel_decide<NB><<<1, WG, 0, st>>>(c, k, a);
+            if (ev) (void)hipEventRecord(ev[4 * k + 1], st);
             k_lu_apply<NB, P><<<1 + 2 * rest * (NB / lu_rb<NB>()), WG, 0, st>>>(c, k);
             if (rest > 0) {
                 constexpr int PER = NB / upd_bt<NB>();
                 k_lu_update<NB, P><<<(unsigned)rest * rest * PER * PER, WG, 0, st>>>(c, k);
             }
+            if (ev) (void)hipEventRecord(ev[4 * k + 2], st);
             k_qr_step<NB, P><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
             k_qr_rinv<NB, S><<<NB / 4, WG, 0, st>>>(c, k);
+            if (ev) (void)hipEventRecord(ev[4 * k + 3], st);
         }
     }
 

@@ -34,7 +34,7 @@ class Factors:
     """Handle of one hybrid LU-QR factorization (Alg. 1)."""
 
     def __init__(self, A, nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed=0,
-                 forced=None, nsteps=-1, mumps_reading=0):
+                 forced=None, nsteps=-1, mumps_reading=0, timing=False, work=None):
         A = colmajor(A)
         self.N = N = A.shape[0]
         self._lda = N
@@ -42,9 +42,11 @@ class Factors:
         self.n = (N + nb - 1) // nb
         self.precision = precision
         self.opts, self._keep = L.make_opts(nb, criterion, alpha, precision, nrhs_max, seed, forced, nsteps,
-                                            mumps_reading)
+                                            mumps_reading, timing)
         nbytes = L.luqr_workspace_bytes(N, self.opts)
-        self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        if work is None or work.numel() < nbytes + 256:
+            work = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self.work = work
         base = self.work.data_ptr()
         off = (-base) % 256
         self._wptr = C.c_void_p(base + off)
@@ -89,6 +91,12 @@ class Factors:
 
     def status(self):
         return L.luqr_get_status(self.h)
+
+    def step_times(self):
+        n = self.n
+        p, lu, qr = (np.zeros(n, np.float32) for _ in range(3))
+        L.luqr_get_step_times(self.h, p.ctypes.data, lu.ctypes.data, qr.ctypes.data, n)
+        return p, lu, qr
 
     def export(self):
         F = torch.empty((self.N, self.N), dtype=torch.float64, device="cuda").t()  # column-major

@@ -29,7 +29,7 @@ def test_library_exports_every_symbol():
 
 def test_struct_layouts_match_header():
     from paper_1401_5522_amd import _lib
-    assert C.sizeof(_lib.luqr_opts) == 48
+    assert C.sizeof(_lib.luqr_opts) == 56
     assert _lib.luqr_opts.forced.offset == 32
     assert C.sizeof(_lib.luqr_status) == 40
     assert _lib.luqr_status.ir_eta.offset == 24
