@@ -71,8 +71,8 @@ typedef struct {
     int32_t nsteps;      /* run only the first nsteps panel steps (< 0: all); a partial
                             factorization cannot be solved with */
     int32_t mumps_reading; /* 0 (default): estimate_max(j) = away_max(j) * prod_{i<j} growth(i) */
-    int32_t timing;      /* nonzero: record HIP events around each step's panel, LU-branch and
-                            QR-branch kernels (read back with luqr_get_step_times) */
+    int32_t timing;      /* nonzero: record HIP events between the kernels of each step
+                            (read back with luqr_get_step_times) */
     int32_t reserved;
 } luqr_opts;
 
@@ -130,14 +130,21 @@ int luqr_get_decisions(luqr_factors f, int8_t *dec, double *s, double *m, double
 /* Read the device status (waits for the handle's stream). */
 int luqr_get_status(luqr_factors f, luqr_status *st);
 
-/* Per-step kernel durations in milliseconds, from the HIP events recorded on
- * the factorization stream when opts.timing was set: panel[k] (GETRF copy,
- * tile norms, triangular inverses, inverse norm, decision), lu[k] (the LU
- * branch kernels) and qr[k] (the QR branch kernels), k < n.  A branch that the
- * decision skipped still appears with the few microseconds its early-exit
- * launch takes.  Arrays may be NULL.  Waits for the stream.  Returns
+/* Per-step kernel durations in milliseconds, from HIP events recorded on the
+ * factorization stream when opts.timing was set.  t (host, 5 n floats) receives
+ * for each step k < n, at t[5 k + p]:
+ *   p = 0  panel: GETRF on the diagonal-tile copy, tile norms, triangular
+ *          inverses, inverse norm and decision
+ *   p = 1  LU Eliminate and Apply (A_ik U^-1, L^-1 P A_kj)
+ *   p = 2  LU trailing update (A_ij -= A_ik A_kj)
+ *   p = 3  QR step: GEQRT, TSQRT, UNMQR and TSMQR in their single launch
+ *   p = 4  R_kk^-1 for the back-substitution of a QR step and the completion
+ *          of its block reflectors' T factors for the solve
+ * A phase that the decision skipped still appears, with the few microseconds
+ * its early-exit launch takes.  Waits for the stream.  Returns
  * LUQR_ERR_UNSUPPORTED if the handle was created without timing. */
-int luqr_get_step_times(luqr_factors f, float *panel, float *lu, float *qr, int64_t n);
+#define LUQR_NPHASE 5
+int luqr_get_step_times(luqr_factors f, float *t, int64_t n);
 
 /* Copy the factored matrix to dF (device, FP64, N x N, column-major, ldf) in
  * the layout the paper describes in-place (L\U or V\R on the diagonal tiles,

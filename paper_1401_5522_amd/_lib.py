@@ -74,7 +74,7 @@ def lib() -> C.CDLL:
     L.luqr_get_status.restype = C.c_int
     L.luqr_get_status.argtypes = [vp, C.POINTER(luqr_status)]
     L.luqr_get_step_times.restype = C.c_int
-    L.luqr_get_step_times.argtypes = [vp, vp, vp, vp, i64]
+    L.luqr_get_step_times.argtypes = [vp, vp, i64]
     L.luqr_export_factors.restype = C.c_int
     L.luqr_export_factors.argtypes = [vp, vp, i64, vp, vp]
     L.luqr_destroy.restype = None
@@ -137,8 +137,11 @@ def luqr_get_status(h):
     return st
 
 
-def luqr_get_step_times(h, panel, lu, qr, n):
-    return check(lib().luqr_get_step_times(h, panel, lu, qr, n), "luqr_get_step_times")
+NPHASE = 5  # LUQR_NPHASE: panel, LU apply, LU update, QR step, R^-1
+
+
+def luqr_get_step_times(h, t, n):
+    return check(lib().luqr_get_step_times(h, t, n), "luqr_get_step_times")
 
 
 def luqr_export_factors(h, dF, ldf, ipiv, stream):

@@ -16,7 +16,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libluqr.so")
-SOURCES = ["api.hip", "inst_p64.hip", "inst_p32.hip", "inst_pb16.hip", "batched.hip"]
+# (source, object name, extra flags): inst.hip once per (precision, tile size)
+TILES = {0: (32, 64, 128, 256), 1: (32, 64, 128, 256, 512), 2: (32, 64, 128, 256, 512)}
+UNITS = [("api.hip", "api", []), ("batched.hip", "batched", [])] + [
+    ("inst.hip", f"inst_p{p}_nb{nb}", [f"-DLQ_P={p}", f"-DLQ_NB={nb}"]) for p, nbs in TILES.items() for nb in nbs]
 ARCH = os.environ.get("LUQR_ARCH", "gfx950")
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
@@ -24,9 +27,10 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-I" + os.path.join(ROOT, "include")]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit) -> str:
+    src, name, extra = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         msg = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
@@ -36,10 +40,12 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    jobs = min(len(srcs), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    units = [u for u in UNITS if os.path.exists(os.path.join(CSRC, u[0]))]
+    jobs = min(len(units), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    # the largest tile sizes take longest: start them first
+    units.sort(key=lambda u: -int(u[2][1].split("=")[1]) if u[2] else 0)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(_compile, units))
     tmp = LIB + ".tmp"
     subprocess.check_call(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)

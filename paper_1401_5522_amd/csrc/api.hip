@@ -17,14 +17,14 @@ struct luqr_factors_s {
     hipStream_t stream;
     luqr_opts o;
     int nsteps;
-    std::vector<hipEvent_t> ev;  // 4 per step when opts.timing is set
+    std::vector<hipEvent_t> ev;  // LUQR_NPHASE + 1 per step when opts.timing is set
 };
 
 static const Ops *pick_ops(int nb, int prec) {
     switch (prec) {
-    case LUQR_FP64: return ops_p64(nb);
-    case LUQR_FP32: return ops_p32(nb);
-    case LUQR_BF16: return ops_pb16(nb);
+    case LUQR_FP64: return ops_nb<P64>(nb);
+    case LUQR_FP32: return ops_nb<P32>(nb);
+    case LUQR_BF16: return ops_nb<PB16>(nb);
     default: return nullptr;
     }
 }
@@ -76,7 +76,7 @@ extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_
     f->o.forced = nullptr;
     f->nsteps = (o->nsteps < 0 || o->nsteps > L.n) ? (int)L.n : o->nsteps;
     if (o->timing) {
-        f->ev.resize((size_t)4 * f->nsteps);
+        f->ev.resize((size_t)(LUQR_NPHASE + 1) * f->nsteps);
         for (auto &e : f->ev) {
             hipError_t he = hipEventCreate(&e);
             if (he != hipSuccess) { e = nullptr; luqr_destroy(f); return hip_rc(he); }
@@ -96,6 +96,7 @@ static SolveArgs solve_args(luqr_factors f, int nrhs, const int *gate) {
     s.Y = (double *)(b + f->L.off_Y);
     s.Z = (double *)(b + f->L.off_Z);
     s.X = (double *)(b + f->L.off_X);
+    s.G = (double *)(b + f->L.off_G);
     s.nrhs = nrhs;
     s.gate = gate;
     return s;
@@ -240,18 +241,17 @@ extern "C" int luqr_export_factors(luqr_factors f, double *dF, int64_t ldf, int3
     return 0;
 }
 
-extern "C" int luqr_get_step_times(luqr_factors f, float *panel, float *lu, float *qr, int64_t n) {
+extern "C" int luqr_get_step_times(luqr_factors f, float *t, int64_t n) {
     if (!f) return -1;
-    if (n < 0 || n > f->nsteps) return -5;
+    if (!t) return -2;
+    if (n < 0 || n > f->nsteps) return -3;
     if (f->ev.empty()) return LUQR_ERR_UNSUPPORTED;
     hipError_t e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) return hip_rc(e);
     for (int64_t k = 0; k < n; ++k) {
-        hipEvent_t *v = &f->ev[4 * k];
-        float t;
-        if (panel) { if ((e = hipEventElapsedTime(&t, v[0], v[1])) != hipSuccess) return hip_rc(e); panel[k] = t; }
-        if (lu) { if ((e = hipEventElapsedTime(&t, v[1], v[2])) != hipSuccess) return hip_rc(e); lu[k] = t; }
-        if (qr) { if ((e = hipEventElapsedTime(&t, v[2], v[3])) != hipSuccess) return hip_rc(e); qr[k] = t; }
+        hipEvent_t *v = &f->ev[(size_t)(LUQR_NPHASE + 1) * k];
+        for (int p = 0; p < LUQR_NPHASE; ++p)
+            if ((e = hipEventElapsedTime(&t[LUQR_NPHASE * k + p], v[p], v[p + 1])) != hipSuccess) return hip_rc(e);
     }
     return 0;
 }

@@ -102,6 +102,29 @@ LQ_DEV void wave_argmax(double &v, int &idx) {
     argmax_step<3>(v, idx); argmax_step<4>(v, idx); argmax_step<5>(v, idx);
 }
 
+// Sum a 16-vector across the 64 lanes of a wave: stages 0-3 exchange halves
+// of the remaining entries (lane bit 5, 4, 3, 2 choosing the upper half),
+// stages 4-5 add the last partners.  On return lane l holds the total of
+// entry (l >> 2) & 15.
+template <int ST, int H, class S> LQ_DEV void xhalf(S (&v)[16]) {
+    const bool up = (lane_id() >> xbit<ST>()) & 1;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        S send = up ? v[i] : v[i + H];
+        S keep = up ? v[i + H] : v[i];
+        v[i] = keep + xlane<ST>(send);
+    }
+}
+template <class S>
+LQ_DEV S xreduce16(S (&v)[16]) {
+    xhalf<0, 8>(v);
+    xhalf<1, 4>(v);
+    xhalf<2, 2>(v);
+    xhalf<3, 1>(v);
+    S t = v[0] + xlane<4>(v[0]);
+    return t + xlane<5>(t);
+}
+
 // Order LDS traffic between lanes of one wave (no workgroup barrier).
 LQ_DEV void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -159,10 +182,10 @@ struct Layout {
     int64_t N, n, nb, Np;
     int prec, nrhs_max;
     int64_t sz_S;  // bytes of a storage element
-    size_t off_At, off_Tf, off_W, off_Linv, off_Dinv, off_ipiv, off_perm, off_zpiv;
+    size_t off_At, off_Tf, off_gram, off_W, off_Linv, off_Dinv, off_ipiv, off_perm, off_zpiv;
     size_t off_dec, off_s, off_m, off_margin, off_status;
     size_t off_tnorm, off_away, off_lmax, off_invpart, off_flags, off_scale;
-    size_t off_Y, off_Z, off_X, off_R, off_D, off_Xd, off_part, off_apart, off_rnorm, off_anorm, off_conv;
+    size_t off_Y, off_Z, off_X, off_R, off_D, off_Xd, off_G, off_part, off_apart, off_rnorm, off_anorm, off_conv;
     size_t total;
     int64_t nparts;  // column chunks of the residual kernel
 };
@@ -178,7 +201,8 @@ inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     L.off_At = take(n * n * t2 * L.sz_S);
-    L.off_Tf = take(n * n * b * IB * L.sz_S);
+    L.off_Tf = take(n * (n + 1) / 2 * t2 * L.sz_S);
+    L.off_gram = take(n * t2 * 8);
     L.off_W = take(n * t2 * 8);
     L.off_Linv = take(n * t2 * 8);
     L.off_Dinv = take(n * t2 * 8);
@@ -203,6 +227,7 @@ inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max) {
     L.off_R = take(Np * r * 8);
     L.off_D = take(Np * r * 8);
     L.off_Xd = take(Np * r * 8);
+    L.off_G = take(Np * r * 8);
     L.nparts = (Np + 2047) / 2048;
     L.off_part = take(L.nparts * Np * r * 8);
     L.off_apart = take(L.nparts * Np * 8);
@@ -216,7 +241,10 @@ inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max) {
 // Device pointers into one workspace, passed by value to every kernel.
 struct Ctx {
     void *At;        // factor tiles, storage precision
-    void *Tf;        // compact-WY T factors: tile (i,k) holds nb x IB (block b at rows b*IB)
+    void *Tf;        // compact-WY T factor of every QR panel tile (i,k), i >= k: nb x nb upper
+                     // triangular, column-major, at tqoff(i,k); the diagonal IB-blocks are the
+                     // per-block factors the QR step uses, the rest is filled after the step
+    double *gram;    // per panel tile of the current QR step: V^T V (nb x nb, upper IB-blocks)
     double *W;       // per step: FP64 copy of A_kk, factored in place (L\U)
     double *Linv;    // per step: L_kk^{-1} (unit lower)
     double *Dinv;    // per step: inverse of the upper-triangular diagonal factor (U or R)
@@ -235,13 +263,15 @@ struct Ctx {
     int64_t N, n;
     int nb;
     LQ_HD int64_t toff(int64_t i, int64_t j) const { return (j * n + i) * (int64_t)nb * nb; }
+    // T factor of panel tile (i,k), i >= k: panels packed one after another
+    LQ_HD int64_t tqoff(int64_t i, int64_t k) const { return (k * n - k * (k - 1) / 2 + (i - k)) * (int64_t)nb * nb; }
     LQ_HD int msize(int64_t k) const { return (int)((k < n - 1) ? nb : N - (n - 1) * (int64_t)nb); }
 };
 
 inline Ctx make_ctx(const Layout &L, void *base) {
     char *b = (char *)base;
     Ctx c;
-    c.At = b + L.off_At; c.Tf = b + L.off_Tf; c.W = (double *)(b + L.off_W);
+    c.At = b + L.off_At; c.Tf = b + L.off_Tf; c.gram = (double *)(b + L.off_gram); c.W = (double *)(b + L.off_W);
     c.Linv = (double *)(b + L.off_Linv); c.Dinv = (double *)(b + L.off_Dinv);
     c.ipiv = (int *)(b + L.off_ipiv); c.perm = (int *)(b + L.off_perm); c.zpiv = (int *)(b + L.off_zpiv);
     c.dec = (int *)(b + L.off_dec); c.s = (double *)(b + L.off_s); c.m = (double *)(b + L.off_m);

@@ -24,8 +24,8 @@ template <int NB, int P>
 struct Eng {
     typedef typename Tr<P>::S S;
 
-    // ev (optional): 4 events per step, recorded before the panel kernels, the
-    // LU-branch kernels, the QR-branch kernels and after the last of them.
+    // ev (optional): LUQR_NPHASE + 1 events per step, one before each phase of
+    // luqr_get_step_times and one after the last.
     static void factor(const Ctx &c, const Layout &L, const double *A, int64_t lda, const luqr_opts &o, int nsteps,
                        hipStream_t st, hipEvent_t *ev) {
         const int n = (int)c.n;
@@ -35,9 +35,10 @@ struct Eng {
         k_fill_u32<<<nblk((int64_t)n * n), WG, 0, st>>>(c.tmax, (int64_t)n * n);
         k_to_tiles<S><<<nblk(L.Np * L.Np), WG, 0, st>>>(A, lda, c.N, c.n, NB, (S *)c.At);
         constexpr int B = NB < 64 ? NB : 64;
+        constexpr int E = LUQR_NPHASE + 1;
         for (int k = 0; k < nsteps; ++k) {
             const int rest = n - k - 1;
-            if (ev) (void)hipEventRecord(ev[4 * k + 0], st);
+            if (ev) (void)hipEventRecord(ev[E * k + 0], st);
             k_panel_a<NB, S><<<n - k, WG, 0, st>>>(c, k);
             k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
             k_panel_invnorm<NB><<<(NB / B) * (NB / B), WG, 0, st>>>(c, k);
@@ -48,26 +49,35 @@ struct Eng {
             a.seed = o.seed;
             a.mumps_reading = o.mumps_reading;
             k_panel_decide<NB><<<1, WG, 0, st>>>(c, k, a);
-            if (ev) (void)hipEventRecord(ev[4 * k + 1], st);
+            if (ev) (void)hipEventRecord(ev[E * k + 1], st);
             k_lu_apply<NB, P><<<1 + 2 * rest * (NB / lu_rb<NB>()), WG, 0, st>>>(c, k);
+            if (ev) (void)hipEventRecord(ev[E * k + 2], st);
             if (rest > 0) {
                 constexpr int PER = NB / upd_bt<NB>();
                 k_lu_update<NB, P><<<(unsigned)rest * rest * PER * PER, WG, 0, st>>>(c, k);
             }
-            if (ev) (void)hipEventRecord(ev[4 * k + 2], st);
+            if (ev) (void)hipEventRecord(ev[E * k + 3], st);
             k_qr_step<NB, P><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
+            if (ev) (void)hipEventRecord(ev[E * k + 4], st);
             k_qr_rinv<NB, S><<<NB / 4, WG, 0, st>>>(c, k);
-            if (ev) (void)hipEventRecord(ev[4 * k + 3], st);
+            if constexpr (NB > IB) {
+                k_qr_gram<NB, P><<<dim3(qr_npairs<NB>(), n - k), WG, 0, st>>>(c, k);
+                k_qr_tfull<NB, P><<<n - k, WG, 0, st>>>(c, k);
+            }
+            if (ev) (void)hipEventRecord(ev[E * k + 5], st);
         }
     }
 
     static void solve(const Ctx &c, const Layout &L, SolveArgs s, hipStream_t st) {
         const int n = (int)c.n;
-        const unsigned ch = (unsigned)((s.nrhs + RQ - 1) / RQ);
+        const unsigned ch = (unsigned)((s.nrhs + rq<NB>() - 1) / rq<NB>());
         for (int k = 0; k < n; ++k) {
+            const int rest = n - k - 1;
             k_fwd_lu_a<NB><<<dim3(1, ch), WG, 0, st>>>(c, s, k);
-            if (n - k - 1 > 0) k_fwd_lu_b<NB, S><<<dim3(n - k - 1, ch), WG, 0, st>>>(c, s, k);
-            k_fwd_qr<NB, S><<<dim3(1, ch), WG, 0, st>>>(c, s, k);
+            if (rest > 0) k_fwd_lu_b<NB, S><<<dim3(rest, ch), WG, 0, st>>>(c, s, k);
+            if (rest > 0) k_fwd_qr_g<NB, S><<<dim3(rest, ch), WG, 0, st>>>(c, s, k);
+            k_fwd_qr_chain<NB, S><<<dim3(1, ch), CHAIN_WG, 0, st>>>(c, s, k);
+            if (rest > 0) k_fwd_qr_u<NB, S><<<dim3(rest, ch), WG, 0, st>>>(c, s, k);
         }
         for (int k = n - 1; k >= 0; --k) {
             k_bwd_a<NB><<<dim3(1, ch), WG, 0, st>>>(c, s, k);
@@ -85,8 +95,23 @@ struct Eng {
     }
 };
 
-const Ops *ops_p64(int nb);
-const Ops *ops_p32(int nb);
-const Ops *ops_pb16(int nb);
+// Launch tables, one per (tile size, precision) instantiation (inst.hip).
+template <int NB, int P> const Ops *eng_ops();
+#define LQ_DECLARE(NB, P) template <> const Ops *eng_ops<NB, P>();
+LQ_DECLARE(32, P64) LQ_DECLARE(64, P64) LQ_DECLARE(128, P64) LQ_DECLARE(256, P64)
+LQ_DECLARE(32, P32) LQ_DECLARE(64, P32) LQ_DECLARE(128, P32) LQ_DECLARE(256, P32) LQ_DECLARE(512, P32)
+LQ_DECLARE(32, PB16) LQ_DECLARE(64, PB16) LQ_DECLARE(128, PB16) LQ_DECLARE(256, PB16) LQ_DECLARE(512, PB16)
+#undef LQ_DECLARE
+
+template <int P> const Ops *ops_nb(int nb) {
+    switch (nb) {
+    case 32: return eng_ops<32, P>();
+    case 64: return eng_ops<64, P>();
+    case 128: return eng_ops<128, P>();
+    case 256: return eng_ops<256, P>();
+    case 512: if constexpr (P != P64) return eng_ops<512, P>(); else return nullptr;
+    default: return nullptr;
+    }
+}
 
 }  // namespace lq

@@ -14,8 +14,11 @@
 // 16 columns over all nb rows) for the whole chain, so A_kj never leaves the
 // chip between the n-k-1 updates it receives.
 // Reflectors use the LAPACK convention: beta = -sign(alpha)||x||, tau = 0
-// when the tail is zero.  Compact-WY factors are kept per IB = 32 columns:
-// block b of T(i,k) sits at rows b*IB.. of the nb x IB tile Tf(i,k).
+// when the tail is zero.  The QR step builds the compact-WY factor per IB = 32
+// columns: block b of T(i,k) is the diagonal block (b*IB.., b*IB..) of the
+// nb x nb factor of tile (i,k); k_qr_gram and k_qr_tfull fill the blocks above
+// the diagonal afterwards, so the solve can apply each tile's reflectors as
+// one block (I - V T V^T).
 #pragma once
 #include <utility>
 
@@ -24,29 +27,6 @@
 namespace lq {
 
 template <class S> LQ_DEV S sq(S x) { return x * x; }
-
-// Sum a 16-vector across the 64 lanes of a wave: stages 0-3 exchange halves
-// of the remaining entries (lane bit 5, 4, 3, 2 choosing the upper half),
-// stages 4-5 add the last partners.  On return lane l holds the total of
-// entry (l >> 2) & 15.
-template <int ST, int H, class S> LQ_DEV void xhalf(S (&v)[16]) {
-    const bool up = (lane_id() >> xbit<ST>()) & 1;
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        S send = up ? v[i] : v[i + H];
-        S keep = up ? v[i + H] : v[i];
-        v[i] = keep + xlane<ST>(send);
-    }
-}
-template <class S>
-LQ_DEV S xreduce16(S (&v)[16]) {
-    xhalf<0, 8>(v);
-    xhalf<1, 4>(v);
-    xhalf<2, 2>(v);
-    xhalf<3, 1>(v);
-    S t = v[0] + xlane<4>(v[0]);
-    return t + xlane<5>(t);
-}
 
 template <int NB> constexpr int qr_rpt() { return NB > 256 ? 2 : 1; }  // panel rows per thread
 
@@ -352,10 +332,10 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
             if (bail) return;
             __atomic_thread_fence(__ATOMIC_ACQUIRE);
         }
-        S *Ti = Tf + c.toff(i, k) / NB * IB;
+        S *Ti = Tf + c.tqoff(i, k);
         if (i == k) {
             panel_qr<NB, S, false>(Akk, c0, nullptr, Ys, Ts, pl);
-            for (int e = tid; e < IB * IB; e += WG) Ti[(c0 + e % IB) + (e / IB) * NB] = Ts[e];
+            for (int e = tid; e < IB * IB; e += WG) Ti[(c0 + e % IB) + (c0 + e / IB) * NB] = Ts[e];
             panel_trailing<NB, PP, false>(Akk, nullptr, b, Ys, Ts);
         } else {
             S *Aik = At + c.toff(i, k);
@@ -368,7 +348,7 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
             for (int e = tid; e < IB * IB; e += WG) {
                 const int p = e % IB, q = e / IB;
                 if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[e];
-                Ti[(c0 + p) + q * NB] = Ts[e];
+                Ti[(c0 + p) + (c0 + q) * NB] = Ts[e];
             }
             panel_trailing<NB, PP, true>(Aik, Akk, b, Ys, Ts);
         }
@@ -406,7 +386,7 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
     __shared__ int bail;
     {  // UNMQR on the strip of A_kj: explicit V blocks of the GEQRT tile
         const S *V = At + c.toff(k, k);
-        const S *T = Tf + c.toff(k, k) / NB * IB;
+        const S *T = Tf + c.tqoff(k, k);
         if (active) {
 #pragma unroll
             for (int rb = 0; rb < NB / 16; ++rb)
@@ -424,7 +404,7 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
                 S v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : V[r + (c0 + q) * NB]);
                 Ys[q * LDY + r] = v;
             }
-            for (int e = tid; e < IB * IB; e += WG) Ts[(e / IB) * IB + e % IB] = T[(c0 + e % IB) + (e / IB) * NB];
+            for (int e = tid; e < IB * IB; e += WG) Ts[(e / IB) * IB + e % IB] = T[(c0 + e % IB) + (c0 + e / IB) * NB];
             __syncthreads();
             if (active) apply_block<NB, P, false>(bot, nullptr, b, Ys, Ts);
             __syncthreads();
@@ -439,7 +419,7 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
     for (int i = k + 1; i < c.n; ++i) {
         S *Aij = At + c.toff(i, j);
         const S *Y = At + c.toff(i, k);
-        const S *T = Tf + c.toff(i, k) / NB * IB;
+        const S *T = Tf + c.tqoff(i, k);
         if (active) {
 #pragma unroll
             for (int rb = 0; rb < NB / 16; ++rb)
@@ -456,7 +436,7 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
                 int r = e % NB, q = e / NB;
                 Ys[q * LDY + r] = Y[r + (c0 + q) * NB];
             }
-            for (int e = tid; e < IB * IB; e += WG) Ts[(e / IB) * IB + e % IB] = T[(c0 + e % IB) + (e / IB) * NB];
+            for (int e = tid; e < IB * IB; e += WG) Ts[(e / IB) * IB + e % IB] = T[(c0 + e % IB) + (c0 + e / IB) * NB];
             __syncthreads();
             if (active) apply_block<NB, P, true>(bot, topc, b, Ys, Ts);
             __syncthreads();
@@ -467,6 +447,91 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Aij[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB] = (S)bot[rb][r];
         }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Completion of the nb x nb compact-WY factors of a QR step's panel tiles
+// (needed by the solve only).  With V = [V_0 .. V_{B-1}] split in IB-column
+// blocks and Q = Q_0 Q_1 .. Q_{B-1}, Q_b = I - V_b T_b V_b^T, the product is
+// I - V T V^T with T upper triangular, diagonal blocks T_b, and (Schreiber and
+// Van Loan's block recurrence) for each b the block column above the diagonal
+//     T(0:c, c:c+IB) = -T(0:c, 0:c) (V(:,0:c)^T V(:,c:c+IB)) T_b,   c = b IB.
+// For the TS tiles V = [I; Y] and the identity parts of different columns do
+// not overlap, so V(:,0:c)^T V(:,c:) = Y(:,0:c)^T Y(:,c:); for the GEQRT tile
+// V is the unit-lower part of the factored diagonal tile.
+// ---------------------------------------------------------------------------
+template <int NB> constexpr int qr_npairs() { return (NB / IB) * (NB / IB - 1) / 2; }
+
+// Gram blocks G(a, b) = V_a^T V_b, a < b, in FP64 (MFMA), one IB x IB block per
+// workgroup; grid (pairs, n-k).
+template <int NB, int P>
+__global__ __launch_bounds__(WG) void k_qr_gram(Ctx c, int k) {
+    if (c.dec[k] != 0) return;
+    typedef typename Tr<P>::S S;
+    __shared__ __attribute__((aligned(16))) char smem[mma_lds_bytes<P64, IB, IB, 16>()];
+    int p = blockIdx.x, bb = 1;
+    while (p >= bb) { p -= bb; ++bb; }
+    const int a0 = p * IB, b0 = bb * IB;
+    const int t = blockIdx.y, i = k + t;
+    const S *V = (const S *)c.At + c.toff(i, k);
+    const bool ts = i > k;
+    auto v = [&](int r, int col) -> double {
+        if (ts) return (double)V[r + (size_t)col * NB];
+        return r < col ? 0.0 : (r == col ? 1.0 : (double)V[r + (size_t)col * NB]);
+    };
+    Tr<P64>::acc acc[1][1];
+    acc_zero<P64, IB, IB, 2, 2>(acc);
+    wg_mma<P64, IB, IB, 2, 2, 16>(
+        acc, NB, [&](int r, int kk) { return v(kk, a0 + r); }, [&](int kk, int cc) { return v(kk, b0 + cc); }, smem);
+    double *G = c.gram + (size_t)t * NB * NB;
+    acc_foreach<P64, IB, IB, 2, 2>(acc, [&](int r, int cc, double x) { G[(a0 + r) + (size_t)(b0 + cc) * NB] = x; });
+}
+
+// Off-diagonal blocks of T, block column by block column; one workgroup per
+// panel tile, grid n-k.  FP64 arithmetic, storage precision result.
+template <int NB, int P>
+__global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k) {
+    if (c.dec[k] != 0) return;
+    typedef typename Tr<P>::S S;
+    constexpr int MR = (NB - IB) / 8;  // rows a per thread at most
+    __shared__ double Gs[(NB - IB) * IB];  // G(0:c, c:c+IB), then Y1 = T(0:c,0:c) G(...)
+    __shared__ double Tb[IB * IB];
+    const int t = blockIdx.x, i = k + t;
+    S *T = (S *)c.Tf + c.tqoff(i, k);
+    const double *G = c.gram + (size_t)t * NB * NB;
+    const int tid = threadIdx.x, q = tid & (IB - 1), a1 = tid / IB;
+    for (int b = 1; b < NB / IB; ++b) {
+        const int c0 = b * IB;
+        for (int e = tid; e < c0 * IB; e += WG) Gs[e] = G[(e / IB) + (size_t)(c0 + e % IB) * NB];  // Gs[a*IB + q]
+        for (int e = tid; e < IB * IB; e += WG) {
+            const int pp = e / IB, qq = e % IB;
+            Tb[e] = pp <= qq ? (double)T[(c0 + pp) + (size_t)(c0 + qq) * NB] : 0.0;  // Tb[p*IB + q]
+        }
+        __syncthreads();
+        double y1[MR];
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+            const int a = a1 + 8 * m;
+            double acc = 0.0;
+            if (a < c0)
+                for (int a2 = a; a2 < c0; ++a2) acc += (double)T[a + (size_t)a2 * NB] * Gs[a2 * IB + q];
+            y1[m] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+            const int a = a1 + 8 * m;
+            if (a < c0) Gs[a * IB + q] = y1[m];
+        }
+        __syncthreads();
+        for (int a = a1; a < c0; a += 8) {
+            double acc = 0.0;
+            for (int pp = 0; pp <= q; ++pp) acc += Gs[a * IB + pp] * Tb[pp * IB + q];
+            T[a + (size_t)(c0 + q) * NB] = (S)(-acc);
+        }
+        __syncthreads();
     }
 }
 

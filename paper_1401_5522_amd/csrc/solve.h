@@ -11,12 +11,14 @@
 
 namespace lq {
 
-constexpr int RQ = 16;  // right-hand sides per workgroup
+// Right-hand sides per workgroup (grid.y chunks of this many columns).
+template <int NB> constexpr int rq() { return NB >= 512 ? 8 : 16; }
 
 struct SolveArgs {
     double *Y;        // working right-hand sides (Np x nrhs)
     double *Z;        // forward results z_k
     double *X;        // solution
+    double *G;        // QR-step scratch (Np x nrhs): Y_ik^T y_i, then the block products W_i
     int nrhs;
     const int *gate;  // may be null
 };
@@ -43,6 +45,7 @@ static __global__ void k_rhs_out(const double *X, double *B, int64_t ldb, int64_
 template <int NB>
 static __global__ __launch_bounds__(WG) void k_fwd_lu_a(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 1 || gated(s.gate)) return;
+    constexpr int RQ = rq<NB>();
     __shared__ double ys[NB * RQ];
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
     const int64_t Np = c.n * NB;
@@ -65,6 +68,7 @@ static __global__ __launch_bounds__(WG) void k_fwd_lu_a(Ctx c, SolveArgs s, int 
 template <int NB, class S>
 static __global__ __launch_bounds__(WG) void k_fwd_lu_b(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 1 || gated(s.gate)) return;
+    constexpr int RQ = rq<NB>();
     __shared__ double zs[NB * RQ];
     const int i = k + 1 + blockIdx.x;
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
@@ -87,94 +91,155 @@ static __global__ __launch_bounds__(WG) void k_fwd_lu_b(Ctx c, SolveArgs s, int 
     }
 }
 
-// Apply one compact-WY block (IB reflectors starting at row c0 of the
-// eliminator) to right-hand-side blocks held in LDS.  TS form (Yb given):
-// W = T^T (zk[c0..c0+IB) + Y^T yi); zk[c0..] -= W; yi -= Y W.
-// GEQRT form (Yb null, V = unit-lower columns of the diagonal tile):
-// W = T^T V^T zk; zk -= V W.
-template <int NB, class S>
-LQ_DEV void fwd_block(double *zk, double *yi, const S *Vt, const S *Yb, const S *Tt, int c0, int nq, double *Wsh) {
-    const int tid = threadIdx.x;
-    for (int e = tid; e < IB * nq; e += WG) {
-        int lq = e % IB, q = e / IB;
-        double acc;
-        if (Yb) {
-            acc = zk[q * NB + c0 + lq];
-            for (int r = 0; r < NB; ++r) acc += (double)Yb[r + (c0 + lq) * NB] * yi[q * NB + r];
-        } else {
-            acc = zk[q * NB + c0 + lq];
-            for (int r = c0 + lq + 1; r < NB; ++r) acc += (double)Vt[r + (c0 + lq) * NB] * zk[q * NB + r];
-        }
-        Wsh[q * IB + lq] = acc;
-    }
-    __syncthreads();
-    double w2[(IB * RQ + WG - 1) / WG];
-    int u = 0;
-    for (int e = tid; e < IB * nq; e += WG, ++u) {
-        int lq = e % IB, q = e / IB;
-        double acc = 0.0;
-        for (int p = 0; p <= lq; ++p) acc += (double)Tt[(c0 + p) + lq * NB] * Wsh[q * IB + p];
-        w2[u] = acc;
-    }
-    __syncthreads();
-    u = 0;
-    for (int e = tid; e < IB * nq; e += WG, ++u) Wsh[(e / IB) * IB + e % IB] = w2[u];
-    __syncthreads();
-    if (Yb) {
-        for (int e = tid; e < IB * nq; e += WG) zk[(e / IB) * NB + c0 + e % IB] -= Wsh[e];
-        for (int e = tid; e < NB * nq; e += WG) {
-            int r = e % NB, q = e / NB;
-            double acc = 0.0;
-            for (int lq = 0; lq < IB; ++lq) acc += (double)Yb[r + (c0 + lq) * NB] * Wsh[q * IB + lq];
-            yi[q * NB + r] -= acc;
-        }
-    } else {
-        for (int e = tid; e < (NB - c0) * nq; e += WG) {
-            int r = c0 + e % (NB - c0), q = e / (NB - c0);
-            double acc = 0.0;
-            const int lm = r - c0 < IB ? r - c0 : IB - 1;
-            for (int lq = 0; lq <= lm; ++lq) {
-                double v = (r == c0 + lq) ? 1.0 : (double)Vt[r + (c0 + lq) * NB];
-                acc += v * Wsh[q * IB + lq];
+// out[q*ldo + r] = sum_c M(c, r) u[q*NB + c] for r < NB, q < nq: the products
+// M^T u with M an nb x nb column-major tile, where by MODE
+//   0: M as stored;  1: upper triangle of M (c <= r);
+//   2: unit-lower trapezoid (c > r: stored value, c == r: 1, c < r: 0).
+// Each wave takes groups of 16 columns; lanes run down the rows (coalesced),
+// keep 16 partial sums and combine them with one transpose-reduction.
+template <int NB, int NW, int MODE, class S>
+LQ_DEV void cols_dot(const S *M, const double *u, int nq, double *out, int64_t ldo) {
+    const int l = lane_id(), w = (int)(threadIdx.x >> 6);
+    for (int g = w; g < NB / 16; g += NW) {
+        const int r0 = 16 * g;
+        const int mlo = MODE == 2 ? r0 / 64 : 0;
+        const int mhi = MODE == 1 ? (r0 + 15) / 64 : (NB - 1) / 64;
+        for (int q = 0; q < nq; ++q) {
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = 0.0;
+            for (int m = mlo; m <= mhi; ++m) {
+                const int cc = 64 * m + l;
+                if (NB < 64 && cc >= NB) break;  // nb = 32: the upper half-wave idles
+                const double uc = u[q * NB + cc];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int r = r0 + j;
+                    double a;
+                    if constexpr (MODE == 0) a = (double)M[cc + (size_t)r * NB];
+                    else if constexpr (MODE == 1) a = cc <= r ? (double)M[cc + (size_t)r * NB] : 0.0;
+                    else a = cc > r ? (double)M[cc + (size_t)r * NB] : (cc == r ? 1.0 : 0.0);
+                    v[j] += a * uc;
+                }
             }
-            zk[q * NB + r] -= acc;
+            const double tot = xreduce16(v);
+            if ((l & 3) == 0) out[q * ldo + r0 + ((l >> 2) & 15)] = tot;
         }
     }
-    __syncthreads();
 }
 
-// QR step: z_k = Q^T-chain applied to (y_k, y_{k+1}, ..., y_{n-1}); one
-// workgroup per rhs chunk walks the flat tree in order.
+// QR step, part 1 (one workgroup per tile row i > k): g_i = Y_ik^T y_i.
 template <int NB, class S>
-static __global__ __launch_bounds__(WG) void k_fwd_qr(Ctx c, SolveArgs s, int k) {
+static __global__ __launch_bounds__(WG) void k_fwd_qr_g(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 0 || gated(s.gate)) return;
-    __shared__ double zk[NB * RQ];
-    __shared__ double yi[NB * RQ];
-    __shared__ double Wsh[IB * RQ];
+    constexpr int RQ = rq<NB>();
+    __shared__ double ys[NB * RQ];
+    const int i = k + 1 + blockIdx.x;
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
     const int64_t Np = c.n * NB;
-    const S *At = (const S *)c.At;
-    const S *Tf = (const S *)c.Tf;
-    for (int e = threadIdx.x; e < NB * nq; e += WG) zk[e] = s.Y[k * NB + e % NB + (q0 + e / NB) * Np];
+    for (int e = threadIdx.x; e < NB * nq; e += WG) ys[e] = s.Y[i * NB + e % NB + (q0 + e / NB) * Np];
     __syncthreads();
-    const S *Tkk = Tf + c.toff(k, k) / NB * IB;
-    for (int c0 = 0; c0 < NB; c0 += IB) fwd_block<NB, S>(zk, yi, At + c.toff(k, k), nullptr, Tkk, c0, nq, Wsh);
-    for (int i = k + 1; i < c.n; ++i) {
-        for (int e = threadIdx.x; e < NB * nq; e += WG) yi[e] = s.Y[i * NB + e % NB + (q0 + e / NB) * Np];
-        __syncthreads();
-        const S *Y = At + c.toff(i, k);
-        const S *T = Tf + c.toff(i, k) / NB * IB;
-        for (int c0 = 0; c0 < NB; c0 += IB) fwd_block<NB, S>(zk, yi, nullptr, Y, T, c0, nq, Wsh);
-        for (int e = threadIdx.x; e < NB * nq; e += WG) s.Y[i * NB + e % NB + (q0 + e / NB) * Np] = yi[e];
-        __syncthreads();
+    cols_dot<NB, WG / 64, 0, S>((const S *)c.At + c.toff(i, k), ys, nq, s.G + i * NB + q0 * Np, Np);
+}
+
+// QR step, part 2 (one workgroup per rhs chunk): the flat tree applied to the
+// eliminator row.  First z = Q_kk^T y_k = z - V T^T V^T z (GEQRT tile), then
+// for i = k+1.. in order, with the full TS factor of tile (i,k),
+//   w_i = T_ik^T (z + g_i),  z -= w_i,
+// which is the top half of [z; y_i] <- Q_ik^T [z; y_i] (V = [I; Y_ik]); the
+// bottom half y_i -= Y_ik w_i is independent of the chain and left to part 3.
+// Only the triangular T factors are read inside the chain.
+constexpr int CHAIN_WG = 1024;
+
+template <int NB, class S>
+static __global__ __launch_bounds__(CHAIN_WG) void k_fwd_qr_chain(Ctx c, SolveArgs s, int k) {
+    if (c.dec[k] != 0 || gated(s.gate)) return;
+    constexpr int RQ = rq<NB>(), NW = CHAIN_WG / 64;
+    constexpr int PER = (NB * RQ + CHAIN_WG - 1) / CHAIN_WG;
+    __shared__ double x[NB * RQ], u[NB * RQ], w[NB * RQ];
+    const int tid = threadIdx.x;
+    const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
+    const int64_t Np = c.n * NB;
+    const S *At = (const S *)c.At, *Tf = (const S *)c.Tf;
+    const S *V = At + c.toff(k, k);
+    auto gidx = [&](int i, int e) { return (int64_t)i * NB + e % NB + (int64_t)(q0 + e / NB) * Np; };
+    for (int e = tid; e < NB * nq; e += CHAIN_WG) x[e] = s.Y[gidx(k, e)];
+    __syncthreads();
+    cols_dot<NB, NW, 2, S>(V, x, nq, u, NB);  // u = V^T z
+    __syncthreads();
+    cols_dot<NB, NW, 1, S>(Tf + c.tqoff(k, k), u, nq, w, NB);  // w = T^T u
+    __syncthreads();
+    for (int e = tid; e < NB * nq; e += CHAIN_WG) {  // z -= V w
+        const int r = e % NB, q = e / NB;
+        double acc = w[q * NB + r];
+        for (int cc = 0; cc < r; ++cc) acc += (double)V[r + (size_t)cc * NB] * w[q * NB + cc];
+        x[e] -= acc;
     }
-    for (int e = threadIdx.x; e < NB * nq; e += WG) s.Z[k * NB + e % NB + (q0 + e / NB) * Np] = zk[e];
+    double gn[PER];  // g_i of the next tile row, loaded one iteration ahead
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = tid + p * CHAIN_WG;
+        gn[p] = (k + 1 < c.n && e < NB * nq) ? s.G[gidx(k + 1, e)] : 0.0;
+    }
+    for (int i = k + 1; i < c.n; ++i) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int e = tid + p * CHAIN_WG;
+            if (e < NB * nq) u[e] = x[e] + gn[p];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int e = tid + p * CHAIN_WG;
+            gn[p] = (i + 1 < c.n && e < NB * nq) ? s.G[gidx(i + 1, e)] : 0.0;
+        }
+        cols_dot<NB, NW, 1, S>(Tf + c.tqoff(i, k), u, nq, w, NB);
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int e = tid + p * CHAIN_WG;
+            if (e < NB * nq) {
+                x[e] -= w[e];
+                s.G[gidx(i, e)] = w[e];
+            }
+        }
+    }
+    for (int e = tid; e < NB * nq; e += CHAIN_WG) s.Z[gidx(k, e)] = x[e];
+}
+
+// QR step, part 3 (one workgroup per tile row i > k): y_i -= Y_ik w_i.
+template <int NB, class S>
+static __global__ __launch_bounds__(WG) void k_fwd_qr_u(Ctx c, SolveArgs s, int k) {
+    if (c.dec[k] != 0 || gated(s.gate)) return;
+    constexpr int RQ = rq<NB>();
+    __shared__ double ws[NB * RQ];
+    const int i = k + 1 + blockIdx.x;
+    const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
+    const int64_t Np = c.n * NB;
+    for (int e = threadIdx.x; e < NB * nq; e += WG) ws[e] = s.G[i * NB + e % NB + (q0 + e / NB) * Np];
+    __syncthreads();
+    const S *Y = (const S *)c.At + c.toff(i, k);
+    for (int r = threadIdx.x; r < NB; r += WG) {
+        double acc[RQ];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
+        for (int cc = 0; cc < NB; ++cc) {
+            const double a = (double)Y[r + (size_t)cc * NB];
+#pragma unroll
+            for (int q = 0; q < RQ; ++q)
+                if (q < nq) acc[q] += a * ws[q * NB + cc];
+        }
+#pragma unroll
+        for (int q = 0; q < RQ; ++q)
+            if (q < nq) s.Y[i * NB + r + (q0 + q) * Np] -= acc[q];
+    }
 }
 
 // Back-substitution, part 1: x_k = D_k^{-1} z_k (D_k = U or R of step k).
 template <int NB>
 static __global__ __launch_bounds__(WG) void k_bwd_a(Ctx c, SolveArgs s, int k) {
     if (gated(s.gate)) return;
+    constexpr int RQ = rq<NB>();
     __shared__ double zs[NB * RQ];
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
     const int64_t Np = c.n * NB;
@@ -193,6 +258,7 @@ static __global__ __launch_bounds__(WG) void k_bwd_a(Ctx c, SolveArgs s, int k) 
 template <int NB, class S>
 static __global__ __launch_bounds__(WG) void k_bwd_b(Ctx c, SolveArgs s, int k) {
     if (gated(s.gate)) return;
+    constexpr int RQ = rq<NB>();
     __shared__ double xs[NB * RQ];
     const int i = blockIdx.x;
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);

@@ -92,11 +92,14 @@ class Factors:
     def status(self):
         return L.luqr_get_status(self.h)
 
+    PHASES = ("panel", "lu_apply", "lu_update", "qr_step", "qr_rinv")
+
     def step_times(self):
-        n = self.n
-        p, lu, qr = (np.zeros(n, np.float32) for _ in range(3))
-        L.luqr_get_step_times(self.h, p.ctypes.data, lu.ctypes.data, qr.ctypes.data, n)
-        return p, lu, qr
+        """(n, 5) array of per-step phase durations in ms (columns: PHASES);
+        needs timing=True at construction."""
+        t = np.zeros((self.n, L.NPHASE), np.float32)
+        L.luqr_get_step_times(self.h, t.ctypes.data, self.n)
+        return t
 
     def export(self):
         F = torch.empty((self.N, self.N), dtype=torch.float64, device="cuda").t()  # column-major
