@@ -108,15 +108,22 @@ int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_opts *opts,
 /* Overwrite dB (device, N x nrhs, leading dimension ldb, FP64) with A^{-1} B
  * using the stored factors: forward replay of the step transformations
  * (Sec. 2.4, second pass) then block back-substitution.  The arithmetic is
- * the factor precision; B and the result are FP64.  nrhs <= opts.nrhs_max. */
+ * FP64 over factors in their storage precision; B and the result are FP64.
+ * nrhs <= opts.nrhs_max.  The first solve on a handle waits once for the
+ * factorization to finish and reads its decision sequence, so that every
+ * solve launches only the kernels of the branch each step took; after that
+ * the call only enqueues. */
 int luqr_solve(luqr_factors f, int64_t nrhs, double *dB, int64_t ldb, void *stream);
 
 /* Mixed-precision solve with FP64 iterative refinement: x0 = solve(b), then
- * up to max_iter times r = b - A x (FP64, from dA), d = solve(r) in the factor
- * precision, x += d (FP64), stopping on the device once every column has
+ * up to max_iter times r = b - A x (FP64, from dA), d = solve(r) with the
+ * stored factors, x += d (FP64), stopping once every column has
  * ||r||_inf <= N * 1e-16 * ||A||_inf ||x||_inf.  dA is the FP64 matrix that
- * was factored; dB is read, dX (N x nrhs, ldx) written.  Iteration count and
- * final backward error are reported by luqr_get_status. */
+ * was factored; dB is read, dX (N x nrhs, ldx) written.  The convergence test
+ * runs on the device; the host reads its flag after each residual (a wait on
+ * `stream`) to stop enqueuing, so this call returns when at most the final
+ * copy to dX is still in flight.  Iteration count and final backward error
+ * are reported by luqr_get_status. */
 int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda, int64_t nrhs,
                        const double *dB, int64_t ldb, double *dX, int64_t ldx,
                        int32_t max_iter, void *stream);

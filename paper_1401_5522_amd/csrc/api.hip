@@ -18,7 +18,27 @@ struct luqr_factors_s {
     luqr_opts o;
     int nsteps;
     std::vector<hipEvent_t> ev;  // LUQR_NPHASE + 1 per step when opts.timing is set
+    std::vector<int> hdec;       // decision sequence, read once by the first solve
 };
+
+static int hip_rc(hipError_t e) { return e == hipSuccess ? 0 : LUQR_ERR_HIP - (int)e; }
+
+
+// The decisions are final once the factorization is done; the first solve
+// waits for it once and keeps them, so each later solve launches only the
+// kernels of the branch every step took.
+static int host_decisions(luqr_factors f, const int **out) {
+    if (f->hdec.empty()) {
+        std::vector<int> d((size_t)f->L.n);
+        hipError_t e = hipStreamSynchronize(f->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(d.data(), (char *)f->base + f->L.off_dec, d.size() * sizeof(int), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_rc(e);
+        f->hdec.swap(d);
+    }
+    *out = f->hdec.data();
+    return 0;
+}
 
 static const Ops *pick_ops(int nb, int prec) {
     switch (prec) {
@@ -44,8 +64,6 @@ static int check_opts(int64_t N, const luqr_opts *o, int pos_opts) {
     return 0;
 }
 
-static int hip_rc(hipError_t e) { return e == hipSuccess ? 0 : LUQR_ERR_HIP - (int)e; }
-
 extern "C" int64_t luqr_workspace_bytes(int64_t N, const luqr_opts *o) {
     if (N < 1) return -1;
     int rc = check_opts(N, o, 2);
@@ -53,6 +71,7 @@ extern "C" int64_t luqr_workspace_bytes(int64_t N, const luqr_opts *o) {
     Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max);
     return (int64_t)L.total;
 }
+
 
 extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_opts *o, void *dWork,
                            int64_t work_bytes, void *stream, luqr_factors *out) {
@@ -109,10 +128,13 @@ extern "C" int luqr_solve(luqr_factors f, int64_t nrhs, double *dB, int64_t ldb,
     if (ldb < f->L.N) return -4;
     if (f->nsteps < f->L.n) return LUQR_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
+    const int *hdec;
+    int rc = host_decisions(f, &hdec);
+    if (rc) return rc;
     SolveArgs s = solve_args(f, (int)nrhs, nullptr);
     (void)hipGetLastError();
     k_rhs_in<<<nblk(f->L.Np * nrhs), WG, 0, st>>>(dB, ldb, s.Y, f->L.N, f->L.Np, (int)nrhs, nullptr);
-    f->ops->solve(f->c, f->L, s, st);
+    f->ops->solve(f->c, f->L, s, hdec, st);
     k_rhs_out<<<nblk(f->L.N * nrhs), WG, 0, st>>>(s.X, dB, ldb, f->L.N, f->L.Np, (int)nrhs);
     return hip_rc(hipGetLastError());
 }
@@ -131,6 +153,9 @@ extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda,
     if (f->nsteps < f->L.n) return LUQR_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const Layout &L = f->L;
+    const int *hdec;
+    int rc0 = host_decisions(f, &hdec);
+    if (rc0) return rc0;
     char *b = (char *)f->base;
     int *conv = (int *)(b + L.off_conv);
     double *R = (double *)(b + L.off_R);
@@ -147,7 +172,7 @@ extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda,
     // x0 = solve(b): solve writes its result into X; keep the iterate in Xk
     SolveArgs s = solve_args(f, nq, nullptr);
     k_rhs_in<<<nblk(total), WG, 0, st>>>(dB, ldb, s.Y, L.N, L.Np, nq, nullptr);
-    f->ops->solve(f->c, L, s, st);
+    f->ops->solve(f->c, L, s, hdec, st);
     hipError_t ce = hipMemcpyAsync(Xk, s.X, total * sizeof(double), hipMemcpyDeviceToDevice, st);
     if (ce != hipSuccess) return hip_rc(ce);
     const dim3 rgrid(nblk(L.N), (unsigned)L.nparts, (unsigned)((nq + RQR - 1) / RQR));
@@ -159,10 +184,16 @@ extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda,
                                                   it == 0 ? apart : nullptr, Xk, R, norms, conv);
         k_ir_check<<<1, 64, 0, st>>>(norms, nq, L.N, conv, f->c.st, last ? 1 : 0);
         if (last) break;
+        // stop enqueuing once the test has passed (one small read per iteration)
+        int done = 0;
+        hipError_t ce2 = hipMemcpyAsync(&done, conv, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (ce2 == hipSuccess) ce2 = hipStreamSynchronize(st);
+        if (ce2 != hipSuccess) return hip_rc(ce2);
+        if (done) break;
         SolveArgs sr = solve_args(f, nq, conv);
         k_rhs_in<<<nblk(total), WG, 0, st>>>(R, L.Np, sr.Y, L.Np, L.Np, nq, conv);
         sr.X = D;
-        f->ops->solve(f->c, L, sr, st);
+        f->ops->solve(f->c, L, sr, hdec, st);
         k_ir_update<<<nblk(total), WG, 0, st>>>(Xk, D, total, conv);
     }
     k_rhs_out<<<nblk(L.N * nrhs), WG, 0, st>>>(Xk, dX, ldx, L.N, L.Np, nq);

@@ -81,13 +81,51 @@ template <int ST> LQ_DEV double xlane(double x) {
 // lane bit that distinguishes a lane from its stage-ST partner
 template <int ST> constexpr int xbit() { return 5 - ST; }
 
+// Exchange across lane bit 5 (ST = 0) or bit 4 (ST = 1) without LDS:
+// v_permlane32_swap / v_permlane16_swap(a, b) swap the upper half-wave
+// (odd 16-lane rows) of a with the lower half-wave (even rows) of b.  With
+// a = x and b = y the two results hold, in some order, x of this lane and x
+// of its partner for lanes with the bit clear, y of this lane and y of its
+// partner for lanes with it set; so their sum (or max) is the xor-exchange
+// reduction step, and with x = y = v it is v combined with v of the partner
+// (checked on every lane with a layout probe).
+template <int ST> LQ_DEV void swap_pair(int a, int b, int &r0, int &r1) {
+    static_assert(ST == 0 || ST == 1, "permlane swaps exist for lane bits 5 and 4");
+    if constexpr (ST == 0) {
+        auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        r0 = (int)r[0]; r1 = (int)r[1];
+    } else {
+        auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        r0 = (int)r[0]; r1 = (int)r[1];
+    }
+}
+// x of this lane plus x (lanes with bit clear) / y (bit set) of the partner,
+// laid out as described above: returns keep + received for every lane.
+template <int ST> LQ_DEV float swap_add(float x, float y) {
+    int r0, r1;
+    swap_pair<ST>(__float_as_int(x), __float_as_int(y), r0, r1);
+    return __int_as_float(r0) + __int_as_float(r1);
+}
+template <int ST> LQ_DEV double swap_add(double x, double y) {
+    int l0, l1, h0, h1;
+    swap_pair<ST>(__double2loint(x), __double2loint(y), l0, l1);
+    swap_pair<ST>(__double2hiint(x), __double2hiint(y), h0, h1);
+    return __hiloint2double(h0, l0) + __hiloint2double(h1, l1);
+}
+template <int ST> LQ_DEV double swap_max(double v) {
+    int l0, l1, h0, h1;
+    swap_pair<ST>(__double2loint(v), __double2loint(v), l0, l1);
+    swap_pair<ST>(__double2hiint(v), __double2hiint(v), h0, h1);
+    return fmax(__hiloint2double(h0, l0), __hiloint2double(h1, l1));
+}
+
 template <class T> LQ_DEV T wave_sum(T v) {
-    v += xlane<0>(v); v += xlane<1>(v); v += xlane<2>(v);
+    v = swap_add<0>(v, v); v = swap_add<1>(v, v); v += xlane<2>(v);
     v += xlane<3>(v); v += xlane<4>(v); v += xlane<5>(v);
     return v;
 }
 LQ_DEV double wave_max(double v) {
-    v = fmax(v, xlane<0>(v)); v = fmax(v, xlane<1>(v)); v = fmax(v, xlane<2>(v));
+    v = swap_max<0>(v); v = swap_max<1>(v); v = fmax(v, xlane<2>(v));
     v = fmax(v, xlane<3>(v)); v = fmax(v, xlane<4>(v)); v = fmax(v, xlane<5>(v));
     return v;
 }
@@ -107,12 +145,17 @@ LQ_DEV void wave_argmax(double &v, int &idx) {
 // stages 4-5 add the last partners.  On return lane l holds the total of
 // entry (l >> 2) & 15.
 template <int ST, int H, class S> LQ_DEV void xhalf(S (&v)[16]) {
-    const bool up = (lane_id() >> xbit<ST>()) & 1;
+    if constexpr (ST <= 1) {
 #pragma unroll
-    for (int i = 0; i < H; ++i) {
-        S send = up ? v[i] : v[i + H];
-        S keep = up ? v[i + H] : v[i];
-        v[i] = keep + xlane<ST>(send);
+        for (int i = 0; i < H; ++i) v[i] = swap_add<ST>(v[i], v[i + H]);
+    } else {
+        const bool up = (lane_id() >> xbit<ST>()) & 1;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            S send = up ? v[i] : v[i + H];
+            S keep = up ? v[i + H] : v[i];
+            v[i] = keep + xlane<ST>(send);
+        }
     }
 }
 template <class S>

@@ -14,7 +14,7 @@ namespace lq {
 struct Ops {
     void (*factor)(const Ctx &, const Layout &, const double *A, int64_t lda, const luqr_opts &, int nsteps,
                    hipStream_t, hipEvent_t *ev);
-    void (*solve)(const Ctx &, const Layout &, SolveArgs, hipStream_t);
+    void (*solve)(const Ctx &, const Layout &, SolveArgs, const int *hdec, hipStream_t);
     void (*export_factors)(const Ctx &, const Layout &, double *F, int64_t ldf, hipStream_t);
 };
 
@@ -68,20 +68,26 @@ struct Eng {
         }
     }
 
-    static void solve(const Ctx &c, const Layout &L, SolveArgs s, hipStream_t st) {
+    // hdec: the decision sequence on the host; only the chosen branch of each
+    // step is launched (the kernels check the device copy as well).
+    static void solve(const Ctx &c, const Layout &L, SolveArgs s, const int *hdec, hipStream_t st) {
         const int n = (int)c.n;
         const unsigned ch = (unsigned)((s.nrhs + rq<NB>() - 1) / rq<NB>());
+        constexpr int RPT = NB / mv_rb<NB>();  // row blocks per tile
         for (int k = 0; k < n; ++k) {
             const int rest = n - k - 1;
-            k_fwd_lu_a<NB><<<dim3(1, ch), WG, 0, st>>>(c, s, k);
-            if (rest > 0) k_fwd_lu_b<NB, S><<<dim3(rest, ch), WG, 0, st>>>(c, s, k);
-            if (rest > 0) k_fwd_qr_g<NB, S><<<dim3(rest, ch), WG, 0, st>>>(c, s, k);
-            k_fwd_qr_chain<NB, S><<<dim3(1, ch), CHAIN_WG, 0, st>>>(c, s, k);
-            if (rest > 0) k_fwd_qr_u<NB, S><<<dim3(rest, ch), WG, 0, st>>>(c, s, k);
+            if (hdec[k] == 1) {
+                k_fwd_lu_a<NB><<<dim3(RPT, ch), WG, 0, st>>>(c, s, k);
+                if (rest > 0) k_fwd_lu_b<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
+            } else {
+                if (rest > 0) k_fwd_qr_g<NB, S><<<dim3(rest * qs<NB>(), ch), WG, 0, st>>>(c, s, k);
+                k_fwd_qr_chain<NB, S><<<dim3(1, ch), CHAIN_WG, 0, st>>>(c, s, k);
+                if (rest > 0) k_fwd_qr_u<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
+            }
         }
         for (int k = n - 1; k >= 0; --k) {
-            k_bwd_a<NB><<<dim3(1, ch), WG, 0, st>>>(c, s, k);
-            if (k > 0) k_bwd_b<NB, S><<<dim3(k, ch), WG, 0, st>>>(c, s, k);
+            k_bwd_a<NB><<<dim3(RPT, ch), WG, 0, st>>>(c, s, k);
+            if (k > 0) k_bwd_b<NB, S><<<dim3(k * RPT, ch), WG, 0, st>>>(c, s, k);
         }
     }
 

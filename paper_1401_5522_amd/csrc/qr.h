@@ -37,54 +37,38 @@ template <int NB> constexpr int qr_rpt() { return NB > 256 ? 2 : 1; }  // panel 
 //   TS = true:  TSQRT panel of [R; A]: R's diagonal block (Rb, LDS) holds the
 //               pivots, A's whole column is the reflector tail Y.
 // Column q runs as its own instantiation (compile-time q), so every register
-// index is static.  One 32-entry reduction per column yields both the
-// products v_q^T a_j (j > q, the columns still to update) and the Gram
-// entries v_j^T v_q (j < q) that extend the compact-WY factor T.
+// index is static.  One cross-workgroup reduction per column: with x the
+// unscaled tail of column q (after reflectors 0..q-1), it sums x^T x, x^T a_j
+// for the columns j > q still to update, and x^T v_j for the reflectors
+// j < q.  The Householder scale s = 1/(alpha - beta) is applied afterwards:
+// v_q^T a_j = base_j + s x^T a_j, where base_j is the pivot-row entry (R(q, j)
+// for TS, A(pivot, j) for GEQRT), and the same form gives the Gram entries
+// v_j^T v_q that extend the compact-WY factor T.  The reduction of column q+1
+// is formed right after column q's update, so each column costs one barrier
+// (partial sums ping-pong between two LDS buffers).
 // On return Ys holds V (explicit zeros/ones for GEQRT) and Ts holds T.
 // ---------------------------------------------------------------------------
 struct PanelLds {
-    double red1[4];
-    double red2[32 * 4];  // [j][wave]
-    double alpha;
+    double red[2][IB * 4];  // [buffer][j][wave]
+    double prow[2][IB];     // GEQRT: pivot row of the column being reduced
 };
 
+// Partial sums of column q's reduction into pl->red[q & 1]; for GEQRT the
+// owner of the pivot row also publishes it.
 template <int NB, class S, bool TS, int Q>
-LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *pl) {
+LQ_DEV void qr_reduce(S (&P)[qr_rpt<NB>()][IB], int c0, PanelLds *pl) {
     constexpr int RPT = qr_rpt<NB>();
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
-    const int pr = c0 + Q;  // GEQRT pivot row
-    S ss = 0;
+    const int pr = c0 + Q;
+    S x[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int r = tid + 256 * u;
-        if (TS ? r < NB : (r > pr && r < NB)) ss += sq(P[u][Q]);
-        if (!TS && r == pr) pl->alpha = (double)P[u][Q];
-    }
-    ss = wave_sum(ss);
-    if (l == 0) pl->red1[w] = (double)ss;
-    __syncthreads();  // A: norms and the pivot are visible
-    ss = (S)((pl->red1[0] + pl->red1[1]) + (pl->red1[2] + pl->red1[3]));
-    const S alpha = TS ? Rb[Q * IB + Q] : (S)pl->alpha;
-    S rq[IB];  // TS: row Q of R's diagonal block, issued early to overlap the scalar work
+        x[u] = (TS ? r < NB : (r > pr && r < NB)) ? P[u][Q] : (S)0;
+        if (!TS && r == pr) {
 #pragma unroll
-    for (int j = 0; j < IB; ++j) rq[j] = (TS && j > Q) ? Rb[j * IB + Q] : (S)0;
-    S tau = 0, beta = alpha, scal = 1;
-    if (ss != (S)0) {
-        const S nrm = sqrt(alpha * alpha + ss);
-        beta = alpha >= (S)0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = (S)1 / (alpha - beta);
-    }
-    S vq[RPT];
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        const int r = tid + 256 * u;
-        S v;
-        if (TS) v = r < NB ? P[u][Q] * scal : (S)0;
-        else v = (r == pr) ? (S)1 : ((r > pr && r < NB) ? P[u][Q] * scal : (S)0);
-        vq[u] = v;
-        if (TS ? r < NB : (r > pr && r < NB)) P[u][Q] = v;
-        if (!TS && r == pr) P[u][Q] = beta;
+            for (int j = 0; j < IB; ++j) pl->prow[Q & 1][j] = (double)P[u][j];
+        }
     }
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -93,35 +77,65 @@ LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *
         for (int jj = 0; jj < 16; ++jj) {
             const int j = 16 * half + jj;
             S acc = 0;
-            if (j != Q) {
 #pragma unroll
-                for (int u = 0; u < RPT; ++u) acc += vq[u] * P[u][j];
-                // TS: the pivot row of v_q lives in R (entry 1 at row q): add R(q, j) once
-                if (TS && j > Q && tid == 0) acc += rq[j];
-            }
+            for (int u = 0; u < RPT; ++u) acc += x[u] * P[u][j];
             part[jj] = acc;
         }
         const S tot = xreduce16<S>(part);
-        if ((l & 3) == 0) pl->red2[(16 * half + (l >> 2)) * 4 + w] = (double)tot;
+        if ((l & 3) == 0) pl->red[Q & 1][(16 * half + (l >> 2)) * 4 + w] = (double)tot;
     }
-    __syncthreads();  // B: all partial products visible; alpha and R row q read
-    S d[IB];  // reduced products: all LDS reads issued before any use
+}
+
+// TS: R's row q is read by every thread during column q, so its new values
+// (and beta on the diagonal) are written one barrier later: `pend` carries
+// this thread's write (index into Rb, -1 for none) into the next column.
+template <int NB, class S, bool TS, int Q>
+LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *pl, int &pend_i, S &pend_v) {
+    constexpr int RPT = qr_rpt<NB>();
+    const int tid = threadIdx.x;
+    const int pr = c0 + Q;  // GEQRT pivot row
+    if (TS && pend_i >= 0) Rb[pend_i] = pend_v;
+    const double *red = pl->red[Q & 1];
+    S f[IB];  // x^T a_j, all LDS reads issued before any use
+#pragma unroll
+    for (int j = 0; j < IB; ++j) f[j] = (S)((red[j * 4] + red[j * 4 + 1]) + (red[j * 4 + 2] + red[j * 4 + 3]));
+    S base[IB];
 #pragma unroll
     for (int j = 0; j < IB; ++j) {
-        if (j == Q) { d[j] = 0; continue; }
-        const double *rj = &pl->red2[j * 4];
-        d[j] = (S)((rj[0] + rj[1]) + (rj[2] + rj[3]));
+        if (TS) base[j] = j >= Q ? Rb[j * IB + Q] : (S)0;
+        else base[j] = (S)pl->prow[Q & 1][j];
     }
+    const S ss = f[Q], alpha = base[Q];
+    S tau = 0, beta = alpha, scal = 1;
+    if (ss != (S)0) {
+        const S nrm = sqrt(alpha * alpha + ss);
+        beta = alpha >= (S)0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = (S)1 / (alpha - beta);
+    }
+    S d[IB];  // v_q^T a_j (j > q) and v_j^T v_q (j < q)
+#pragma unroll
+    for (int j = 0; j < IB; ++j) d[j] = j == Q ? (S)0 : base[j] + scal * f[j];
+    S vq[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int r = tid + 256 * u;
+        const bool tail = TS ? r < NB : (r > pr && r < NB);
+        vq[u] = tail ? P[u][Q] * scal : ((!TS && r == pr) ? (S)1 : (S)0);
+        if (tail) P[u][Q] = vq[u];
+        if (!TS && r == pr) P[u][Q] = beta;
+    }
+    pend_i = -1;
+    if (TS && tid == 0) { pend_i = Q * IB + Q; pend_v = beta; }
     if (tau != (S)0) {
 #pragma unroll
         for (int j = Q + 1; j < IB; ++j) {
             const S wj = tau * d[j];
 #pragma unroll
             for (int u = 0; u < RPT; ++u) P[u][j] -= vq[u] * wj;
-            if (TS && tid == j) Rb[j * IB + Q] = rq[j] - wj;
+            if (TS && tid == j) { pend_i = j * IB + Q; pend_v = base[j] - wj; }
         }
     }
-    if (TS && tid == 0) Rb[Q * IB + Q] = beta;
     // T(0:q, q) = -tau T(0:q, 0:q) G(0:q, q), with G(p, q) = v_p^T v_q = d[p]
     if (tid < Q) {
         S acc = 0;
@@ -132,12 +146,24 @@ LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *
     } else if (tid < IB) {
         Ts[Q * IB + tid] = tid == Q ? tau : (S)0;
     }
+    if constexpr (Q + 1 < IB) {
+        qr_reduce<NB, S, TS, Q + 1>(P, c0, pl);
+        __syncthreads();  // column q+1's sums, its pivot row and R's row q+1 are visible
+    }
 }
 
 template <int NB, class S, bool TS, int... Qs>
 LQ_DEV void qr_columns(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *pl,
                        std::integer_sequence<int, Qs...>) {
-    (qr_column<NB, S, TS, Qs>(P, c0, Rb, Ts, pl), ...);
+    qr_reduce<NB, S, TS, 0>(P, c0, pl);
+    __syncthreads();
+    int pend_i = -1;
+    S pend_v = 0;
+    (qr_column<NB, S, TS, Qs>(P, c0, Rb, Ts, pl, pend_i, pend_v), ...);
+    if (TS) {
+        __syncthreads();  // every read of R's last row is done
+        if (pend_i >= 0) Rb[pend_i] = pend_v;
+    }
 }
 
 template <int NB, class S, bool TS>
@@ -264,6 +290,39 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *
                 a[e] = (__bf16)(-Ys[(16 * (e >> 2) + Tr<P>::drow(g, e & 3)) * LDY + 16 * rb + i16]);
             bot[rb] = Tr<PB16>::mma(a, bw, bot[rb]);
         }
+    }
+}
+
+// Stage block reflector b of tile V (column block c0 = b*IB) and its T block
+// into LDS for apply_block: Ys[q*LDY + r] = V(r, c0+q), Ts[q*IB + p] = T(p, q).
+// GEQRT = true makes V unit-lower explicit (zeros above, ones on the
+// diagonal).  Every thread issues all of its loads before the first store.
+template <int NB, class S, bool GEQRT>
+LQ_DEV void stage_block(const S *V, const S *T, int c0, S *Ys, S *Ts) {
+    constexpr int LDY = NB + 1, PY = NB * IB / WG, PT = IB * IB / WG;
+    const int tid = threadIdx.x;
+    S y[PY], t[PT];
+#pragma unroll
+    for (int u = 0; u < PY; ++u) {
+        const int e = tid + WG * u, r = e % NB, q = e / NB;
+        y[u] = V[r + (size_t)(c0 + q) * NB];
+    }
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int e = tid + WG * u;
+        t[u] = T[(c0 + e % IB) + (size_t)(c0 + e / IB) * NB];
+    }
+#pragma unroll
+    for (int u = 0; u < PY; ++u) {
+        const int e = tid + WG * u, r = e % NB, q = e / NB;
+        S v = y[u];
+        if (GEQRT) v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : v);
+        Ys[q * LDY + r] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int e = tid + WG * u;
+        Ts[(e / IB) * IB + e % IB] = t[u];
     }
 }
 
@@ -399,12 +458,7 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
             __syncthreads();
             if (bail) return;
             __atomic_thread_fence(__ATOMIC_ACQUIRE);
-            for (int e = tid; e < NB * IB; e += WG) {
-                int r = e % NB, q = e / NB;
-                S v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : V[r + (c0 + q) * NB]);
-                Ys[q * LDY + r] = v;
-            }
-            for (int e = tid; e < IB * IB; e += WG) Ts[(e / IB) * IB + e % IB] = T[(c0 + e % IB) + (c0 + e / IB) * NB];
+            stage_block<NB, S, true>(V, T, c0, Ys, Ts);
             __syncthreads();
             if (active) apply_block<NB, P, false>(bot, nullptr, b, Ys, Ts);
             __syncthreads();
@@ -432,11 +486,7 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
             __syncthreads();
             if (bail) return;
             __atomic_thread_fence(__ATOMIC_ACQUIRE);
-            for (int e = tid; e < NB * IB; e += WG) {
-                int r = e % NB, q = e / NB;
-                Ys[q * LDY + r] = Y[r + (c0 + q) * NB];
-            }
-            for (int e = tid; e < IB * IB; e += WG) Ts[(e / IB) * IB + e % IB] = T[(c0 + e % IB) + (c0 + e / IB) * NB];
+            stage_block<NB, S, false>(Y, T, c0, Ys, Ts);
             __syncthreads();
             if (active) apply_block<NB, P, true>(bot, topc, b, Ys, Ts);
             __syncthreads();

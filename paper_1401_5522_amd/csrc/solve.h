@@ -41,66 +41,119 @@ static __global__ void k_rhs_out(const double *X, double *B, int64_t ldb, int64_
     B[r + q * ldb] = X[r + q * Np];
 }
 
-// LU step, part 1: z_k = L^{-1} P y_k.  grid.y = rhs chunks.
+// ---------------------------------------------------------------------------
+// Tile times right-hand-side block, by rows: for the RB = min(64, nb) rows
+// [r0, r0+RB) of an nb x nb column-major tile M,
+//   acc(r, q) = sum_c M(r, c) v[q*NB + c]   (v in LDS),
+// restricted by MODE: 0 every c; 1 c >= r (upper triangle);
+// 2 c < r plus a unit diagonal (unit-lower triangle).  The four waves split
+// the columns in quarters; each lane owns one row, loads 16 columns of it
+// (coalesced across lanes) before using them, and the quarters are summed
+// through LDS.  Result for lane l of wave 0: row r0 + l.
+// ---------------------------------------------------------------------------
+template <int NB> constexpr int mv_rb() { return NB < 64 ? NB : 64; }
+
+template <int NB, int MODE, class S, int RQ>
+LQ_DEV bool rows_mv(const S *M, const double *v, int nq, int r0, double (&out)[RQ], double *red) {
+    constexpr int QC = NB / 4, U = QC < 16 ? QC : 16;
+    const int l = lane_id(), w = wave_id();
+    const int r = r0 + l;
+    const bool live = l < mv_rb<NB>();
+    double acc[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
+    if (live) {
+        const S *p = M + r;
+        for (int c0 = w * QC; c0 < (w + 1) * QC; c0 += U) {
+            S a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = p[(size_t)(c0 + u) * NB];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int cc = c0 + u;
+                double x = (double)a[u];
+                if constexpr (MODE == 1) x = cc >= r ? x : 0.0;
+                if constexpr (MODE == 2) x = cc < r ? x : (cc == r ? 1.0 : 0.0);
+#pragma unroll
+                for (int q = 0; q < RQ; ++q)
+                    if (q < nq) acc[q] += x * v[q * NB + cc];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        if (q < nq) red[(w * RQ + q) * 64 + l] = acc[q];
+    __syncthreads();
+    if (w != 0 || !live) return false;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        if (q < nq) out[q] = red[q * 64 + l] + red[(RQ + q) * 64 + l] + red[(2 * RQ + q) * 64 + l] +
+                             red[(3 * RQ + q) * 64 + l];
+    return true;
+}
+
+// LU step, part 1: z_k = L^{-1} P y_k (L^{-1} from the panel, FP64).
+// grid (nb / RB row blocks, rhs chunks).
 template <int NB>
 static __global__ __launch_bounds__(WG) void k_fwd_lu_a(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 1 || gated(s.gate)) return;
     constexpr int RQ = rq<NB>();
     __shared__ double ys[NB * RQ];
+    __shared__ double red[4 * RQ * 64];
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
+    const int r0 = blockIdx.x * mv_rb<NB>();
     const int64_t Np = c.n * NB;
     const int *pm = c.perm + (size_t)k * NB;
-    const double *Li = c.Linv + (size_t)k * NB * NB;
     for (int e = threadIdx.x; e < NB * nq; e += WG) {
-        int r = e % NB, q = e / NB;
+        const int r = e % NB, q = e / NB;
         ys[q * NB + r] = s.Y[k * NB + pm[r] + (q0 + q) * Np];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < NB * nq; e += WG) {
-        int r = e % NB, q = e / NB;
-        double acc = ys[q * NB + r];
-        for (int cc = 0; cc < r; ++cc) acc += Li[r + (size_t)cc * NB] * ys[q * NB + cc];
-        s.Z[k * NB + r + (q0 + q) * Np] = acc;
-    }
+    double out[RQ];
+    if (rows_mv<NB, 2>(c.Linv + (size_t)k * NB * NB, ys, nq, r0, out, red))
+        for (int q = 0; q < nq; ++q) s.Z[k * NB + r0 + lane_id() + (q0 + q) * Np] = out[q];
 }
 
-// LU step, part 2: y_i -= L_ik z_k for i > k (one workgroup per tile row).
+// y_i -= M_i v for the tiles M_i of one tile column (LU: L_ik z_k; QR: Y_ik
+// w_i) or tile row (back-substitution: U_ik x_k).  grid (tiles * nb / RB,
+// rhs chunks); tile t = blockIdx.x / (nb / RB) is tile row i = i0 + t.
+// Source vector: z_k (kind 0), w_i from the QR scratch (kind 1), x_k (kind 2).
+template <int NB, class S, int KIND>
+LQ_DEV void tile_update(const Ctx &c, const SolveArgs &s, int k, int i0, double *dst) {
+    constexpr int RQ = rq<NB>(), RPT = NB / mv_rb<NB>();
+    __shared__ double vs[NB * RQ];
+    __shared__ double red[4 * RQ * 64];
+    const int i = i0 + (int)blockIdx.x / RPT;
+    const int r0 = ((int)blockIdx.x % RPT) * mv_rb<NB>();
+    const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
+    const int64_t Np = c.n * NB;
+    const double *src = KIND == 0 ? s.Z + (int64_t)k * NB : KIND == 1 ? s.G + (int64_t)i * NB : s.X + (int64_t)k * NB;
+    for (int e = threadIdx.x; e < NB * nq; e += WG) vs[e] = src[e % NB + (q0 + e / NB) * Np];
+    __syncthreads();
+    const S *M = (const S *)c.At + c.toff(i, k);
+    double out[RQ];
+    if (rows_mv<NB, 0>(M, vs, nq, r0, out, red))
+        for (int q = 0; q < nq; ++q) dst[(int64_t)i * NB + r0 + lane_id() + (q0 + q) * Np] -= out[q];
+}
+
+// LU step, part 2: y_i -= L_ik z_k for i > k.
 template <int NB, class S>
 static __global__ __launch_bounds__(WG) void k_fwd_lu_b(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 1 || gated(s.gate)) return;
-    constexpr int RQ = rq<NB>();
-    __shared__ double zs[NB * RQ];
-    const int i = k + 1 + blockIdx.x;
-    const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
-    const int64_t Np = c.n * NB;
-    for (int e = threadIdx.x; e < NB * nq; e += WG) zs[e] = s.Z[k * NB + e % NB + (q0 + e / NB) * Np];
-    __syncthreads();
-    const S *L = (const S *)c.At + c.toff(i, k);
-    for (int r = threadIdx.x; r < NB; r += WG) {
-        double acc[RQ];
-        for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
-        for (int cc = 0; cc < NB; ++cc) {
-            double a = (double)L[r + cc * NB];
-#pragma unroll
-            for (int q = 0; q < RQ; ++q)
-                if (q < nq) acc[q] += a * zs[q * NB + cc];
-        }
-#pragma unroll
-        for (int q = 0; q < RQ; ++q)
-            if (q < nq) s.Y[i * NB + r + (q0 + q) * Np] -= acc[q];
-    }
+    tile_update<NB, S, 0>(c, s, k, k + 1, s.Y);
 }
 
-// out[q*ldo + r] = sum_c M(c, r) u[q*NB + c] for r < NB, q < nq: the products
-// M^T u with M an nb x nb column-major tile, where by MODE
+// out[q*ldo + r] = sum_c M(c, r) u[q*NB + c] for r in [rlo, rhi), q < nq: the
+// products M^T u with M an nb x nb column-major tile, where by MODE
 //   0: M as stored;  1: upper triangle of M (c <= r);
 //   2: unit-lower trapezoid (c > r: stored value, c == r: 1, c < r: 0).
-// Each wave takes groups of 16 columns; lanes run down the rows (coalesced),
-// keep 16 partial sums and combine them with one transpose-reduction.
+// Each wave takes groups of 16 columns; lanes run down the rows (coalesced
+// loads, all issued before use, masks applied by select), keep 16 partial
+// sums and combine them with one transpose-reduction.
 template <int NB, int NW, int MODE, class S>
-LQ_DEV void cols_dot(const S *M, const double *u, int nq, double *out, int64_t ldo) {
+LQ_DEV void cols_dot(const S *M, const double *u, int nq, double *out, int64_t ldo, int rlo, int rhi) {
     const int l = lane_id(), w = (int)(threadIdx.x >> 6);
-    for (int g = w; g < NB / 16; g += NW) {
+    for (int g = rlo / 16 + w; g < rhi / 16; g += NW) {
         const int r0 = 16 * g;
         const int mlo = MODE == 2 ? r0 / 64 : 0;
         const int mhi = MODE == 1 ? (r0 + 15) / 64 : (NB - 1) / 64;
@@ -112,14 +165,16 @@ LQ_DEV void cols_dot(const S *M, const double *u, int nq, double *out, int64_t l
                 const int cc = 64 * m + l;
                 if (NB < 64 && cc >= NB) break;  // nb = 32: the upper half-wave idles
                 const double uc = u[q * NB + cc];
+                S a[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) a[j] = M[cc + (size_t)(r0 + j) * NB];
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int r = r0 + j;
-                    double a;
-                    if constexpr (MODE == 0) a = (double)M[cc + (size_t)r * NB];
-                    else if constexpr (MODE == 1) a = cc <= r ? (double)M[cc + (size_t)r * NB] : 0.0;
-                    else a = cc > r ? (double)M[cc + (size_t)r * NB] : (cc == r ? 1.0 : 0.0);
-                    v[j] += a * uc;
+                    double x = (double)a[j];
+                    if constexpr (MODE == 1) x = cc <= r ? x : 0.0;
+                    if constexpr (MODE == 2) x = cc > r ? x : (cc == r ? 1.0 : 0.0);
+                    v[j] += x * uc;
                 }
             }
             const double tot = xreduce16(v);
@@ -128,18 +183,23 @@ LQ_DEV void cols_dot(const S *M, const double *u, int nq, double *out, int64_t l
     }
 }
 
-// QR step, part 1 (one workgroup per tile row i > k): g_i = Y_ik^T y_i.
+// QR step, part 1: g_i = Y_ik^T y_i for i > k.  grid (tiles * QS, rhs
+// chunks): QS workgroups share the nb columns of one tile.
+template <int NB> constexpr int qs() { return NB >= 128 ? 4 : 1; }
+
 template <int NB, class S>
 static __global__ __launch_bounds__(WG) void k_fwd_qr_g(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 0 || gated(s.gate)) return;
-    constexpr int RQ = rq<NB>();
+    constexpr int RQ = rq<NB>(), QS = qs<NB>();
     __shared__ double ys[NB * RQ];
-    const int i = k + 1 + blockIdx.x;
+    const int i = k + 1 + (int)blockIdx.x / QS;
+    const int part = (int)blockIdx.x % QS;
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
     const int64_t Np = c.n * NB;
     for (int e = threadIdx.x; e < NB * nq; e += WG) ys[e] = s.Y[i * NB + e % NB + (q0 + e / NB) * Np];
     __syncthreads();
-    cols_dot<NB, WG / 64, 0, S>((const S *)c.At + c.toff(i, k), ys, nq, s.G + i * NB + q0 * Np, Np);
+    cols_dot<NB, WG / 64, 0, S>((const S *)c.At + c.toff(i, k), ys, nq, s.G + i * NB + q0 * Np, Np,
+                                part * (NB / QS), (part + 1) * (NB / QS));
 }
 
 // QR step, part 2 (one workgroup per rhs chunk): the flat tree applied to the
@@ -165,9 +225,9 @@ static __global__ __launch_bounds__(CHAIN_WG) void k_fwd_qr_chain(Ctx c, SolveAr
     auto gidx = [&](int i, int e) { return (int64_t)i * NB + e % NB + (int64_t)(q0 + e / NB) * Np; };
     for (int e = tid; e < NB * nq; e += CHAIN_WG) x[e] = s.Y[gidx(k, e)];
     __syncthreads();
-    cols_dot<NB, NW, 2, S>(V, x, nq, u, NB);  // u = V^T z
+    cols_dot<NB, NW, 2, S>(V, x, nq, u, NB, 0, NB);  // u = V^T z
     __syncthreads();
-    cols_dot<NB, NW, 1, S>(Tf + c.tqoff(k, k), u, nq, w, NB);  // w = T^T u
+    cols_dot<NB, NW, 1, S>(Tf + c.tqoff(k, k), u, nq, w, NB, 0, NB);  // w = T^T u
     __syncthreads();
     for (int e = tid; e < NB * nq; e += CHAIN_WG) {  // z -= V w
         const int r = e % NB, q = e / NB;
@@ -193,7 +253,7 @@ static __global__ __launch_bounds__(CHAIN_WG) void k_fwd_qr_chain(Ctx c, SolveAr
             const int e = tid + p * CHAIN_WG;
             gn[p] = (i + 1 < c.n && e < NB * nq) ? s.G[gidx(i + 1, e)] : 0.0;
         }
-        cols_dot<NB, NW, 1, S>(Tf + c.tqoff(i, k), u, nq, w, NB);
+        cols_dot<NB, NW, 1, S>(Tf + c.tqoff(i, k), u, nq, w, NB, 0, NB);
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
@@ -207,78 +267,36 @@ static __global__ __launch_bounds__(CHAIN_WG) void k_fwd_qr_chain(Ctx c, SolveAr
     for (int e = tid; e < NB * nq; e += CHAIN_WG) s.Z[gidx(k, e)] = x[e];
 }
 
-// QR step, part 3 (one workgroup per tile row i > k): y_i -= Y_ik w_i.
+// QR step, part 3: y_i -= Y_ik w_i for i > k.
 template <int NB, class S>
 static __global__ __launch_bounds__(WG) void k_fwd_qr_u(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 0 || gated(s.gate)) return;
-    constexpr int RQ = rq<NB>();
-    __shared__ double ws[NB * RQ];
-    const int i = k + 1 + blockIdx.x;
-    const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
-    const int64_t Np = c.n * NB;
-    for (int e = threadIdx.x; e < NB * nq; e += WG) ws[e] = s.G[i * NB + e % NB + (q0 + e / NB) * Np];
-    __syncthreads();
-    const S *Y = (const S *)c.At + c.toff(i, k);
-    for (int r = threadIdx.x; r < NB; r += WG) {
-        double acc[RQ];
-#pragma unroll
-        for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
-        for (int cc = 0; cc < NB; ++cc) {
-            const double a = (double)Y[r + (size_t)cc * NB];
-#pragma unroll
-            for (int q = 0; q < RQ; ++q)
-                if (q < nq) acc[q] += a * ws[q * NB + cc];
-        }
-#pragma unroll
-        for (int q = 0; q < RQ; ++q)
-            if (q < nq) s.Y[i * NB + r + (q0 + q) * Np] -= acc[q];
-    }
+    tile_update<NB, S, 1>(c, s, k, k + 1, s.Y);
 }
 
-// Back-substitution, part 1: x_k = D_k^{-1} z_k (D_k = U or R of step k).
+// Back-substitution, part 1: x_k = D_k^{-1} z_k (D_k = U or R of step k;
+// its FP64 inverse is upper triangular).  grid (nb / RB, rhs chunks).
 template <int NB>
 static __global__ __launch_bounds__(WG) void k_bwd_a(Ctx c, SolveArgs s, int k) {
     if (gated(s.gate)) return;
     constexpr int RQ = rq<NB>();
     __shared__ double zs[NB * RQ];
+    __shared__ double red[4 * RQ * 64];
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
+    const int r0 = blockIdx.x * mv_rb<NB>();
     const int64_t Np = c.n * NB;
-    const double *Di = c.Dinv + (size_t)k * NB * NB;
     for (int e = threadIdx.x; e < NB * nq; e += WG) zs[e] = s.Z[k * NB + e % NB + (q0 + e / NB) * Np];
     __syncthreads();
-    for (int e = threadIdx.x; e < NB * nq; e += WG) {
-        int r = e % NB, q = e / NB;
-        double acc = 0.0;
-        for (int cc = r; cc < NB; ++cc) acc += Di[r + (size_t)cc * NB] * zs[q * NB + cc];
-        s.X[k * NB + r + (q0 + q) * Np] = acc;
-    }
+    double out[RQ];
+    if (rows_mv<NB, 1>(c.Dinv + (size_t)k * NB * NB, zs, nq, r0, out, red))
+        for (int q = 0; q < nq; ++q) s.X[k * NB + r0 + lane_id() + (q0 + q) * Np] = out[q];
 }
 
 // Back-substitution, part 2: z_i -= U_ik x_k for i < k.
 template <int NB, class S>
 static __global__ __launch_bounds__(WG) void k_bwd_b(Ctx c, SolveArgs s, int k) {
     if (gated(s.gate)) return;
-    constexpr int RQ = rq<NB>();
-    __shared__ double xs[NB * RQ];
-    const int i = blockIdx.x;
-    const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
-    const int64_t Np = c.n * NB;
-    for (int e = threadIdx.x; e < NB * nq; e += WG) xs[e] = s.X[k * NB + e % NB + (q0 + e / NB) * Np];
-    __syncthreads();
-    const S *U = (const S *)c.At + c.toff(i, k);
-    for (int r = threadIdx.x; r < NB; r += WG) {
-        double acc[RQ];
-        for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
-        for (int cc = 0; cc < NB; ++cc) {
-            double a = (double)U[r + cc * NB];
-#pragma unroll
-            for (int q = 0; q < RQ; ++q)
-                if (q < nq) acc[q] += a * xs[q * NB + cc];
-        }
-#pragma unroll
-        for (int q = 0; q < RQ; ++q)
-            if (q < nq) s.Z[i * NB + r + (q0 + q) * Np] -= acc[q];
-    }
+    tile_update<NB, S, 2>(c, s, k, 0, s.Z);
 }
 
 // ---------------------------------------------------------------------------
