@@ -50,7 +50,10 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=10)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 runs (default: --steps; 0 = skip)")
-    ap.add_argument("--cpu-N", type=int, default=4096, help="matrix size of the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-N", type=int, default=8192, help="matrix size of the oracle sample (0 = skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times (the reference kernel "
+                         "for scaling HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -160,6 +163,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                          "launches": 5}), flush=True)
+        return
     from paper_1401_5522_amd import inputs, solver
     N, nb, prec = args.N, args.nb, args.precision
     n = (N + nb - 1) // nb

@@ -8,7 +8,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libluqr.so")
+LIB_PATH = os.environ.get("LUQR_LIB") or os.path.join(_HERE, "libluqr.so")  # LUQR_LIB: another build of the same ABI
 
 LUQR_ERR_UNSUPPORTED = -900
 LUQR_ERR_HIP = -1000
