@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 runs (default: --steps; 0 = skip)")
     ap.add_argument("--cpu-N", type=int, default=8192, help="matrix size of the oracle sample (0 = skip)")
+    ap.add_argument("--input-cache", default="", metavar="PATH",
+                    help="raw FP64 file of A: loaded if it exists, else written after generation (lets "
+                         "profiled runs skip the factorizations that build U and V)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -78,7 +81,31 @@ def lu_update_flops(n, nb, dec):
     return float(np.sum((dec == 1) * 2.0 * r * r) * nb ** 3)
 
 
-def roofline(n, nb, prec, dec, times):
+KERNEL_SOURCES = ("qr.h", "common.h", "mma.h")
+
+
+def measured_traffic(kernel, N, prec):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte-counter
+    summary of this workload, or None when there is none or the kernel sources
+    have changed since it was taken (sha256 recorded in the summary)."""
+    import hashlib
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"k_qr_step_usv{N}_{prec}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(here, "paper_1401_5522_amd", "csrc", f), "rb").read())
+    m = re.search(r"kernel_source_sha256 = ([0-9a-f]{64})", text)
+    t = re.search(kernel + r": +traffic_bytes_per_launch = ([0-9.e+]+)", text)
+    if not m or not t or m.group(1) != h.hexdigest():
+        return None
+    return float(t.group(1))
+
+
+def roofline(n, nb, prec, dec, times, N):
     """Roofline of the kernel with the largest total time among the two
     contraction kernels.  times: (steps, n, 5) phase durations in ms."""
     tot = times.sum(axis=(0, 1))
@@ -95,6 +122,7 @@ def roofline(n, nb, prec, dec, times):
     per_launch = flops / launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
+    traffic = measured_traffic(KERNEL[phase], N, prec)
     return {
         "kernel": KERNEL[phase],
         "bound": "mfma",
@@ -102,7 +130,7 @@ def roofline(n, nb, prec, dec, times):
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": None,
+        "traffic": traffic,
         "flops_per_launch": per_launch,
         "avg_launch_ms": round(avg_ms, 4),
         "launches_per_step": launches,
@@ -179,8 +207,16 @@ def main():
     K, W = args.steps, args.warmup
     K64 = K if args.fp64_steps is None else args.fp64_steps
 
-    print(f"# generating usv N={N} kappa={args.kappa:g}", file=sys.stderr, flush=True)
-    A = inputs.usv_torch(N, args.kappa, seed=(args.seed,))
+    if args.input_cache and os.path.exists(args.input_cache):
+        print(f"# loading A from {args.input_cache}", file=sys.stderr, flush=True)
+        At = np.fromfile(args.input_cache, dtype=np.float64).reshape(N, N)  # row-major A^T = column-major A
+        A = torch.from_numpy(At).cuda().t()
+        del At
+    else:
+        print(f"# generating usv N={N} kappa={args.kappa:g}", file=sys.stderr, flush=True)
+        A = inputs.usv_torch(N, args.kappa, seed=(args.seed,))
+        if args.input_cache:
+            A.t().cpu().numpy().tofile(args.input_cache)
     B = torch.from_numpy(np.asfortranarray(inputs.rhs(N, args.nrhs, seed=(args.seed,)).reshape(N, -1))).cuda()
     B = B.t().contiguous().t()
     torch.cuda.synchronize()
@@ -217,7 +253,7 @@ def main():
     dec = f.decisions()[0]
     times = np.stack([h[0].step_times() for h in handles])
     eta = backward_error(A, X, B)
-    roof = roofline(n, nb, prec, dec, times)
+    roof = roofline(n, nb, prec, dec, times, N)
     phase_ms = {p: round(float(times[:, :, i].sum(axis=1).mean()), 3) for i, p in enumerate(PHASES)}
     fac_ms = float(times.sum(axis=2).sum(axis=1).mean())
     del handles, f, X, work
