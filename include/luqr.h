@@ -165,21 +165,60 @@ void luqr_destroy(luqr_factors f);
 
 /* ---- many independent systems ------------------------------------------ */
 
-/* Workspace for luqr_batched_solve of `batch` systems of sizes N[s] (host). */
-int64_t luqr_batched_workspace_bytes(int64_t batch, const int64_t *N, int64_t nrhs, const luqr_opts *opts);
+/* Solve batch independent systems A_s x_s = b_s (N_s <= 1024, one right-hand
+ * side each) with the hybrid LU-QR algorithm in one persistent launch: each
+ * workgroup takes systems from a queue ordered largest first and runs Alg. 1
+ * (Max or Sum criterion), the solve of Sec. 2.4 and FP64 iterative
+ * refinement on one system.  FP32 tile storage and MFMA contractions
+ * (opts.precision must be LUQR_FP32); tile size 32 or 64 per system.
+ *
+ * Use: luqr_batched_workspace_bytes -> luqr_batched_plan (once per size
+ * set; copies small descriptors into the workspace and waits) ->
+ * luqr_batched_run (only enqueues a counter reset and the persistent kernel,
+ * so it can be captured into a hipGraph and replayed) -> luqr_batched_destroy.
+ * The caller owns the workspace and keeps it alive while the plan is used.
+ */
+typedef struct luqr_batch_s *luqr_batch;
 
-/* Solve batch independent systems A_s x_s = b_s in one persistent launch.
- * N, lda, ldb, ldx are host arrays; dA, dB, dX are device arrays of device
- * pointers (one per system, FP64, column-major).  opts.nb is the tile size
- * (32 or 64); the precision, criterion and alpha apply to every system.
- * With precision != FP64 the solution is refined in FP64 (up to max_iter
- * iterations).  dDec (device, may be NULL) receives the decisions of system s
- * at dDec + s * ceil(Nmax/nb); dEta (device, may be NULL) the backward error
- * of each system. */
-int luqr_batched_solve(int64_t batch, const int64_t *N, const double *const *dA, const int64_t *lda,
-                       const double *const *dB, const int64_t *ldb, double *const *dX, const int64_t *ldx,
-                       int64_t nrhs, const luqr_opts *opts, int32_t max_iter, int8_t *dDec, double *dEta,
-                       void *dWork, int64_t work_bytes, void *stream);
+/* Workspace bytes for the systems of sizes N[s] (host) with tile sizes nb[s]
+ * (host, 32 or 64; NULL = opts.nb for all).  < 0 on invalid input. */
+int64_t luqr_batched_workspace_bytes(int64_t batch, const int64_t *N, const int32_t *nb, const luqr_opts *opts);
+
+/* Plan: N, nb (may be NULL), lda, ldb, ldx are host arrays of batch entries;
+ * dWork (device, 256-byte aligned, >= luqr_batched_workspace_bytes).  Uses
+ * opts.criterion (MAX or SUM), opts.alpha, opts.precision (FP32); max_iter
+ * bounds the refinement per system.  Waits for the descriptor copy.  Returns
+ * LUQR_ERR_UNSUPPORTED for other precisions or criteria. */
+int luqr_batched_plan(int64_t batch, const int64_t *N, const int32_t *nb, const int64_t *lda, const int64_t *ldb,
+                      const int64_t *ldx, const luqr_opts *opts, int32_t max_iter, void *dWork, int64_t work_bytes,
+                      luqr_batch *out);
+
+/* Run: dA, dB, dX are device arrays of batch device pointers (FP64,
+ * column-major with the plan's leading dimensions; x_s written to dX[s]).
+ * dDec (device, may be NULL): decisions of system s at dDec + s *
+ * luqr_batched_decision_stride(plan).  dEta, dIters (device, may be NULL):
+ * backward error ||b-Ax||_inf / (||A||_inf ||x||_inf) and refinement count per
+ * system.  Only enqueues on `stream`. */
+int luqr_batched_run(luqr_batch plan, const double *const *dA, const double *const *dB, double *const *dX,
+                     int8_t *dDec, double *dEta, int32_t *dIters, void *stream);
+
+/* Largest tile count over the plan's systems (stride of dDec). */
+int luqr_batched_decision_stride(luqr_batch plan);
+
+void luqr_batched_destroy(luqr_batch plan);
+
+/* Autotuner: for each size class [64*2^c, 64*2^(c+1)) (c = 0..5, the last
+ * open-ended) time up to `sample` of its systems with tile size 32 and with
+ * 64 (one warm-up and one timed persistent launch each, HIP events) and write
+ * the faster tile size of the class for each system to nb_out (host, batch
+ * entries).  ms_out (host, 12 floats, may be NULL) receives the timings as
+ * [2c] (nb 32) and [2c+1] (nb 64).  Arguments as for plan/run; the systems'
+ * own data are used and dX is overwritten.  Waits for the device.  The
+ * workspace is used as scratch: plan afterwards. */
+int luqr_batched_autotune(int64_t batch, const int64_t *N, const int64_t *lda, const int64_t *ldb,
+                          const int64_t *ldx, const luqr_opts *opts, int32_t max_iter,
+                          const double *const *dA, const double *const *dB, double *const *dX, int32_t sample,
+                          void *dWork, int64_t work_bytes, void *stream, int32_t *nb_out, float *ms_out);
 
 #ifdef __cplusplus
 }

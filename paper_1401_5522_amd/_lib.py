@@ -18,7 +18,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["luqr_workspace_bytes", "luqr_factor", "luqr_solve", "luqr_solve_refined",
             "luqr_get_decisions", "luqr_get_status", "luqr_get_step_times", "luqr_export_factors", "luqr_destroy",
-            "luqr_batched_workspace_bytes", "luqr_batched_solve"]
+            "luqr_batched_workspace_bytes", "luqr_batched_plan", "luqr_batched_run", "luqr_batched_decision_stride",
+            "luqr_batched_destroy", "luqr_batched_autotune"]
 
 
 class luqr_opts(C.Structure):
@@ -80,9 +81,17 @@ def lib() -> C.CDLL:
     L.luqr_destroy.restype = None
     L.luqr_destroy.argtypes = [vp]
     L.luqr_batched_workspace_bytes.restype = i64
-    L.luqr_batched_workspace_bytes.argtypes = [i64, vp, i64, op]
-    L.luqr_batched_solve.restype = C.c_int
-    L.luqr_batched_solve.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, i64, op, i32, vp, vp, vp, i64, vp]
+    L.luqr_batched_workspace_bytes.argtypes = [i64, vp, vp, op]
+    L.luqr_batched_plan.restype = C.c_int
+    L.luqr_batched_plan.argtypes = [i64, vp, vp, vp, vp, vp, op, i32, vp, i64, C.POINTER(vp)]
+    L.luqr_batched_run.restype = C.c_int
+    L.luqr_batched_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.luqr_batched_decision_stride.restype = C.c_int
+    L.luqr_batched_decision_stride.argtypes = [vp]
+    L.luqr_batched_destroy.restype = None
+    L.luqr_batched_destroy.argtypes = [vp]
+    L.luqr_batched_autotune.restype = C.c_int
+    L.luqr_batched_autotune.argtypes = [i64, vp, vp, vp, vp, op, i32, vp, vp, vp, i32, vp, i64, vp, vp, vp]
     _lib = L
     return L
 
@@ -152,11 +161,30 @@ def luqr_destroy(h):
     lib().luqr_destroy(h)
 
 
-def luqr_batched_workspace_bytes(batch, N, nrhs, opts):
-    return check(lib().luqr_batched_workspace_bytes(batch, N, nrhs, C.byref(opts)), "luqr_batched_workspace_bytes")
+def luqr_batched_workspace_bytes(batch, N, nb, opts):
+    return check(lib().luqr_batched_workspace_bytes(batch, N, nb, C.byref(opts)), "luqr_batched_workspace_bytes")
 
 
-def luqr_batched_solve(batch, N, dA, lda, dB, ldb, dX, ldx, nrhs, opts, max_iter, dDec, dEta, dWork,
-                       work_bytes, stream):
-    return check(lib().luqr_batched_solve(batch, N, dA, lda, dB, ldb, dX, ldx, nrhs, C.byref(opts), max_iter,
-                                          dDec, dEta, dWork, work_bytes, stream), "luqr_batched_solve")
+def luqr_batched_plan(batch, N, nb, lda, ldb, ldx, opts, max_iter, dWork, work_bytes):
+    h = C.c_void_p()
+    check(lib().luqr_batched_plan(batch, N, nb, lda, ldb, ldx, C.byref(opts), max_iter, dWork, work_bytes,
+                                  C.byref(h)), "luqr_batched_plan")
+    return h
+
+
+def luqr_batched_run(plan, dA, dB, dX, dDec, dEta, dIters, stream):
+    return check(lib().luqr_batched_run(plan, dA, dB, dX, dDec, dEta, dIters, stream), "luqr_batched_run")
+
+
+def luqr_batched_decision_stride(plan):
+    return check(lib().luqr_batched_decision_stride(plan), "luqr_batched_decision_stride")
+
+
+def luqr_batched_destroy(plan):
+    lib().luqr_batched_destroy(plan)
+
+
+def luqr_batched_autotune(batch, N, lda, ldb, ldx, opts, max_iter, dA, dB, dX, sample, dWork, work_bytes, stream,
+                          nb_out, ms_out):
+    return check(lib().luqr_batched_autotune(batch, N, lda, ldb, ldx, C.byref(opts), max_iter, dA, dB, dX, sample,
+                                             dWork, work_bytes, stream, nb_out, ms_out), "luqr_batched_autotune")

@@ -294,16 +294,3 @@ extern "C" void luqr_destroy(luqr_factors f) {
     delete f;
 }
 
-extern "C" int64_t luqr_batched_workspace_bytes(int64_t batch, const int64_t *N, int64_t nrhs, const luqr_opts *o) {
-    (void)batch; (void)N; (void)nrhs; (void)o;
-    return LUQR_ERR_UNSUPPORTED;
-}
-
-extern "C" int luqr_batched_solve(int64_t batch, const int64_t *N, const double *const *dA, const int64_t *lda,
-                                  const double *const *dB, const int64_t *ldb, double *const *dX, const int64_t *ldx,
-                                  int64_t nrhs, const luqr_opts *o, int32_t max_iter, int8_t *dDec, double *dEta,
-                                  void *dWork, int64_t work_bytes, void *stream) {
-    (void)batch; (void)N; (void)dA; (void)lda; (void)dB; (void)ldb; (void)dX; (void)ldx; (void)nrhs; (void)o;
-    (void)max_iter; (void)dDec; (void)dEta; (void)dWork; (void)work_bytes; (void)stream;
-    return LUQR_ERR_UNSUPPORTED;
-}

@@ -110,3 +110,86 @@ class Factors:
 
 def factor(A, nb, **kw) -> Factors:
     return Factors(A, nb, **kw)
+
+
+class Batch:
+    """Many independent systems solved by the persistent batched kernel
+    (luqr_batched_* in include/luqr.h): FP32 tiles, FP64 refinement, tile size
+    32 or 64 per system.  `As` are 2-D FP64 device tensors (any layout; a
+    column-major copy is kept), `nb` an int or one int per system.  Outputs
+    live in self.X (one FP64 vector per system), self.dec, self.eta, self.iters;
+    run() only enqueues, so it can be captured in a CUDA/HIP graph."""
+
+    def __init__(self, As, nb=64, criterion="max", alpha=1.0, max_iter=10):
+        self.A = [colmajor(A) for A in As]
+        self.batch = B = len(self.A)
+        self.N = np.array([A.shape[0] for A in self.A], np.int64)
+        ld = self.N.copy()
+        self.nb = np.array(nb if np.ndim(nb) else [nb] * B, np.int32)
+        self.opts, self._keep = L.make_opts(int(self.nb[0]), criterion, alpha, "fp32", 1)
+        nbytes = L.luqr_batched_workspace_bytes(B, self.N.ctypes.data, self.nb.ctypes.data, self.opts)
+        self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.work.data_ptr()
+        self._wptr = C.c_void_p(base + (-base) % 256)
+        self._wbytes = nbytes
+        self.plan = L.luqr_batched_plan(B, self.N.ctypes.data, self.nb.ctypes.data, ld.ctypes.data, ld.ctypes.data,
+                                        ld.ctypes.data, self.opts, max_iter, self._wptr, nbytes)
+        self.X = [torch.zeros(int(n), dtype=torch.float64, device="cuda") for n in self.N]
+        self.stride = L.luqr_batched_decision_stride(self.plan)
+        self.dec = torch.full((B * self.stride,), -1, dtype=torch.int8, device="cuda")
+        self.eta = torch.zeros(B, dtype=torch.float64, device="cuda")
+        self.iters = torch.zeros(B, dtype=torch.int32, device="cuda")
+        self._pA = torch.tensor([A.data_ptr() for A in self.A], dtype=torch.int64, device="cuda")
+        self._pX = torch.tensor([x.data_ptr() for x in self.X], dtype=torch.int64, device="cuda")
+        self._pB = None
+        self.Bs = None
+
+    def set_rhs(self, Bs):
+        self.Bs = [b.to(device="cuda", dtype=torch.float64).contiguous() for b in Bs]
+        self._pB = torch.tensor([b.data_ptr() for b in self.Bs], dtype=torch.int64, device="cuda")
+
+    def run(self):
+        L.luqr_batched_run(self.plan, C.c_void_p(self._pA.data_ptr()), C.c_void_p(self._pB.data_ptr()),
+                           C.c_void_p(self._pX.data_ptr()), C.c_void_p(self.dec.data_ptr()),
+                           C.c_void_p(self.eta.data_ptr()), C.c_void_p(self.iters.data_ptr()), _stream())
+
+    def decisions(self):
+        d = self.dec.view(self.batch, self.stride).cpu().numpy()
+        return [d[s, : (int(self.N[s]) + int(self.nb[s]) - 1) // int(self.nb[s])] for s in range(self.batch)]
+
+    def __del__(self):
+        p = getattr(self, "plan", None)
+        if p:
+            try:
+                L.luqr_batched_destroy(p)
+            except Exception:
+                pass
+            self.plan = None
+
+
+def batched_autotune(As, Bs, criterion="max", alpha=1.0, max_iter=10, sample=32):
+    """Tile size per system chosen by luqr_batched_autotune (timed on the
+    device per size class); returns (nb array, timings [class][nb 32, nb 64] in ms)."""
+    A = [colmajor(a) for a in As]
+    Bv = [b.to(device="cuda", dtype=torch.float64).contiguous() for b in Bs]
+    B = len(A)
+    N = np.array([a.shape[0] for a in A], np.int64)
+    ld = N.copy()
+    opts, keep = L.make_opts(64, criterion, alpha, "fp32", 1)
+    n64 = np.full(B, 64, np.int32)
+    n32 = np.full(B, 32, np.int32)
+    nbytes = max(L.luqr_batched_workspace_bytes(B, N.ctypes.data, n64.ctypes.data, opts),
+                 L.luqr_batched_workspace_bytes(B, N.ctypes.data, n32.ctypes.data, opts)) + 24 * B + 4096
+    work = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = work.data_ptr()
+    wptr = C.c_void_p(base + (-base) % 256)
+    X = [torch.zeros(int(n), dtype=torch.float64, device="cuda") for n in N]
+    pA = torch.tensor([a.data_ptr() for a in A], dtype=torch.int64, device="cuda")
+    pB = torch.tensor([b.data_ptr() for b in Bv], dtype=torch.int64, device="cuda")
+    pX = torch.tensor([x.data_ptr() for x in X], dtype=torch.int64, device="cuda")
+    nb_out = np.zeros(B, np.int32)
+    ms = np.zeros(12, np.float32)
+    L.luqr_batched_autotune(B, N.ctypes.data, ld.ctypes.data, ld.ctypes.data, ld.ctypes.data, opts, max_iter,
+                            C.c_void_p(pA.data_ptr()), C.c_void_p(pB.data_ptr()), C.c_void_p(pX.data_ptr()),
+                            sample, wptr, nbytes, _stream(), nb_out.ctypes.data, ms.ctypes.data)
+    return nb_out, ms.reshape(6, 2)
