@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 runs (default: --steps; 0 = skip)")
     ap.add_argument("--cpu-N", type=int, default=8192, help="matrix size of the oracle sample (0 = skip)")
+    ap.add_argument("--workload", default="single", choices=("single", "batched"),
+                    help="single: one large system (default); batched: many small ragged systems in one "
+                         "persistent launch replayed from a graph")
+    ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--input-cache", default="", metavar="PATH",
                     help="raw FP64 file of A: loaded if it exists, else written after generation (lets "
                          "profiled runs skip the factorizations that build U and V)")
@@ -180,6 +184,121 @@ def cpu_baseline(args, solver, torch):
     }
 
 
+def batched_inputs(batch, seed, torch):
+    """N_s ~ U{64..1024}; types cycle over iid N(0,1), N(0,1) + N I and
+    U diag(sigma) V^T with kappa = 1e4 (Haar U, V drawn with torch on the GPU,
+    grouped by size); b_s ~ N(0,1).  All from seeded generators."""
+    from paper_1401_5522_amd import inputs
+    g = inputs.rng(7, seed, batch)
+    N = g.integers(64, 1025, size=batch)
+    kind = np.arange(batch) % 3
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(np.random.SeedSequence([8, seed, batch]).generate_state(1, dtype=np.uint64)[0] & ((1 << 63) - 1)))
+    As = [None] * batch
+    for s_ in range(batch):
+        n = int(N[s_])
+        if kind[s_] == 0:
+            As[s_] = torch.randn(n, n, generator=gen, device="cuda", dtype=torch.float64)
+        elif kind[s_] == 1:
+            As[s_] = torch.randn(n, n, generator=gen, device="cuda", dtype=torch.float64) + n * torch.eye(
+                n, device="cuda", dtype=torch.float64)
+    usv = [s_ for s_ in range(batch) if kind[s_] == 2]
+    by_n = {}
+    for s_ in usv:
+        by_n.setdefault(int(N[s_]), []).append(s_)
+    for n, idx in by_n.items():
+        sig = torch.as_tensor(inputs.sigmas(n, 1e4), device="cuda")
+
+        def haar():
+            Z = torch.randn(len(idx), n, n, generator=gen, device="cuda", dtype=torch.float64)
+            Q, R = torch.linalg.qr(Z)
+            return Q * torch.sign(torch.diagonal(R, dim1=-2, dim2=-1)).unsqueeze(-2)
+        U, V = haar(), haar()
+        M = torch.matmul(U * sig, V.transpose(-2, -1).contiguous())
+        for t, s_ in enumerate(idx):
+            As[s_] = M[t]
+    Bs = [torch.randn(int(n), generator=gen, device="cuda", dtype=torch.float64) for n in N]
+    return N, kind, As, Bs
+
+
+def run_batched(args, torch):
+    from paper_1401_5522_amd import solver
+    K, W = args.steps, args.warmup
+    print(f"# generating {args.batch} systems", file=sys.stderr, flush=True)
+    N, kind, As, Bs = batched_inputs(args.batch, args.seed, torch)
+    torch.cuda.synchronize()
+    print("# autotuning the tile size", file=sys.stderr, flush=True)
+    nb, tune_ms = solver.batched_autotune(As, Bs, criterion=args.criterion, alpha=args.alpha,
+                                          max_iter=args.max_iter, sample=32)
+    bt = solver.Batch(As, nb=nb, criterion=args.criterion, alpha=args.alpha, max_iter=args.max_iter)
+    bt.set_rhs(Bs)
+    bt.run()                                  # eager run: reference results and decisions
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            bt.run()
+    torch.cuda.current_stream().wait_stream(st)
+    for _ in range(W):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(K):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / K
+    kern_ms = e0.elapsed_time(e1) / K
+    eta = bt.eta.cpu().numpy()
+    iters = bt.iters.cpu().numpy()
+    decs = bt.decisions()
+    conv = eta <= N * 1e-16
+    flops_norm = float(np.sum(2.0 * N.astype(np.float64) ** 3 / 3.0))
+    true_fl = 0.0
+    for n_, b_, d in zip(N, nb, decs):
+        r = len(d) - 1 - np.arange(len(d))
+        true_fl += float(np.sum((1.0 + (d == 0)) * (2.0 / 3.0 + 2.0 * r + 2.0 * r * r))) * float(b_) ** 3
+    achieved = true_fl / (kern_ms * 1e-3) / 1e12
+    cpu = None
+    if args.cpu_N > 0:
+        from oracle import oracle as O  # only this leg of the benchmark runs the oracle
+        pick = np.arange(0, args.batch, max(1, args.batch // 1024))[:1024]
+        t0 = time.perf_counter()
+        for s_ in pick:
+            A = As[s_].cpu().numpy()
+            fo = O.factor(A, int(nb[s_]), args.criterion, args.alpha)
+            fo.solve(Bs[s_].cpu().numpy())
+        tc = time.perf_counter() - t0
+        fl = float(np.sum(2.0 * N[pick].astype(np.float64) ** 3 / 3.0))
+        cpu = {"value": round(len(pick) / tc, 3), "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"{len(pick)} of the systems (every {max(1, args.batch // 1024)}th), FP64 oracle factor+solve, "
+                         f"{tc:.1f} s, {fl / tc / 1e12:.4f} TFLOP/s (2N^3/3)"}
+    out = {
+        "metric": "solves/s (batched, ragged N, one persistent launch replayed from a hipGraph)",
+        "value": round(1e3 * args.batch / ms, 2),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched {args.batch} systems N~U[64,1024] gaussian/diag_dominant/usv(kappa=1e4) "
+                               f"{args.criterion} alpha={args.alpha:g} fp32+fp64-IR autotuned nb",
+                   "batch": args.batch, "parallelism": "single GPU"},
+        "tflops_2n3_3": round(flops_norm / (ms * 1e-3) / 1e12, 3),
+        "converged": int(conv.sum()), "eta_max": float(eta.max()), "ir_iters_max": int(iters.max()),
+        "nb_counts": {"32": int((nb == 32).sum()), "64": int((nb == 64).sum())},
+        "autotune_ms": tune_ms.tolist(),
+        "lu_fraction": float(np.mean(np.concatenate(decs))),
+        "roofline": {"kernel": "k_batched", "bound": "mfma", "achieved": round(achieved, 3), "peak": 157.3,
+                     "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4), "traffic": None,
+                     "flops_per_launch": true_fl, "avg_launch_ms": round(kern_ms, 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -200,6 +319,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
                           "launches": 5}), flush=True)
+        return
+    if args.workload == "batched":
+        run_batched(args, torch)
         return
     from paper_1401_5522_amd import inputs, solver
     N, nb, prec = args.N, args.nb, args.precision
