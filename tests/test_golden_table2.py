@@ -35,9 +35,11 @@ def test_fake_rate_is_two_thirds_n_cubed_over_time():
 
 def test_peak_fractions():
     for alpha, t, f, fake, true, fpk, tpk in rows():
-        # printed to 0.1 (rounding 0.05) from rates printed to 0.1 (another 0.05 / 10.91)
-        assert abs(100.0 * fake / PEAK - fpk) <= 0.06, alpha
-        assert abs(100.0 * true / PEAK - tpk) <= 0.06 + 0.005, alpha
+        # percentages printed to 0.1 (0.05), rates printed to 0.1 (0.05 / 10.91), and the
+        # peak printed as an integer (+-0.5 of 1091, up to 0.04 on these fractions)
+        tol = 0.05 + 0.005 + 0.04
+        assert abs(100.0 * fake / PEAK - fpk) <= tol, alpha
+        assert abs(100.0 * true / PEAK - tpk) <= tol, alpha
 
 
 def test_more_qr_steps_never_faster_in_the_table():
