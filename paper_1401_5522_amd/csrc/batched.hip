@@ -339,15 +339,15 @@ LQ_DEV void bsys_factor(const BArgs &a, const BSys &S, char *lds, int8_t *dec_ou
                 float *Tik = btile<NB>(Tf, n, i, k);
                 for (int b = 0; b < NB / IB; ++b) {  // TSQRT(R_kk, A_ik)
                     const int c0 = b * IB;
-                    for (int e = tid; e < IB * IB; e += WG) {
-                        const int p = e % IB, q = e / IB;
+                    for (int e = tid; e < IB * IB; e += WG) {  // row-major R block
+                        const int p = e / IB, q = e % IB;
                         Rb[e] = p <= q ? Akk[(c0 + p) + (c0 + q) * NB] : 0.0f;
                     }
                     __syncthreads();
                     panel_qr<NB, float, true>(Aik, c0, Rb, Ys, Ts, pl);
                     for (int e = tid; e < IB * IB; e += WG) {
                         const int p = e % IB, q = e / IB;
-                        if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[e];
+                        if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[p * IB + q];
                         Tik[(c0 + p) + (c0 + q) * NB] = Ts[e];
                     }
                     panel_trailing<NB, P32, true>(Aik, Akk, b, Ys, Ts);

@@ -34,7 +34,7 @@ template <int NB> constexpr int qr_rpt() { return NB > 256 ? 2 : 1; }  // panel 
 // Producer panel: Householder QR of one IB-column block (c0 = b*IB) with the
 // panel held in registers, thread t owning tile rows t and t+256.
 //   TS = false: GEQRT panel of the tile A (rows c0.., unit-lower V in place).
-//   TS = true:  TSQRT panel of [R; A]: R's diagonal block (Rb, LDS) holds the
+//   TS = true:  TSQRT panel of [R; A]: R's diagonal block (Rb, LDS, row-major) holds the
 //               pivots, A's whole column is the reflector tail Y.
 // Column q runs as its own instantiation (compile-time q), so every register
 // index is static.  One cross-workgroup reduction per column: with x the
@@ -49,8 +49,8 @@ template <int NB> constexpr int qr_rpt() { return NB > 256 ? 2 : 1; }  // panel 
 // On return Ys holds V (explicit zeros/ones for GEQRT) and Ts holds T.
 // ---------------------------------------------------------------------------
 struct PanelLds {
-    double red[2][IB * 4];  // [buffer][j][wave]
-    double prow[2][IB];     // GEQRT: pivot row of the column being reduced
+    double red[2][IB * 4];  // [buffer][j][wave], holding values of the storage type S
+    double prow[2][IB];     // GEQRT: pivot row of the column being reduced (type S)
 };
 
 // Partial sums of column q's reduction into pl->red[q & 1]; for GEQRT the
@@ -67,7 +67,7 @@ LQ_DEV void qr_reduce(S (&P)[qr_rpt<NB>()][IB], int c0, PanelLds *pl) {
         x[u] = (TS ? r < NB : (r > pr && r < NB)) ? P[u][Q] : (S)0;
         if (!TS && r == pr) {
 #pragma unroll
-            for (int j = 0; j < IB; ++j) pl->prow[Q & 1][j] = (double)P[u][j];
+            for (int j = 0; j < IB; ++j) ((S *)pl->prow[Q & 1])[j] = P[u][j];
         }
     }
 #pragma unroll
@@ -82,7 +82,7 @@ LQ_DEV void qr_reduce(S (&P)[qr_rpt<NB>()][IB], int c0, PanelLds *pl) {
             part[jj] = acc;
         }
         const S tot = xreduce16<S>(part);
-        if ((l & 3) == 0) pl->red[Q & 1][(16 * half + (l >> 2)) * 4 + w] = (double)tot;
+        if ((l & 3) == 0) ((S *)pl->red[Q & 1])[(16 * half + (l >> 2)) * 4 + w] = tot;
     }
 }
 
@@ -95,15 +95,15 @@ LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *
     const int tid = threadIdx.x;
     const int pr = c0 + Q;  // GEQRT pivot row
     if (TS && pend_i >= 0) Rb[pend_i] = pend_v;
-    const double *red = pl->red[Q & 1];
-    S f[IB];  // x^T a_j, all LDS reads issued before any use
+    const S *red = (const S *)pl->red[Q & 1];
+    S f[IB];  // x^T a_j: the four waves' partials of column j are adjacent
 #pragma unroll
-    for (int j = 0; j < IB; ++j) f[j] = (S)((red[j * 4] + red[j * 4 + 1]) + (red[j * 4 + 2] + red[j * 4 + 3]));
+    for (int j = 0; j < IB; ++j) f[j] = (red[j * 4] + red[j * 4 + 1]) + (red[j * 4 + 2] + red[j * 4 + 3]);
     S base[IB];
 #pragma unroll
     for (int j = 0; j < IB; ++j) {
-        if (TS) base[j] = j >= Q ? Rb[j * IB + Q] : (S)0;
-        else base[j] = (S)pl->prow[Q & 1][j];
+        if (TS) base[j] = j >= Q ? Rb[Q * IB + j] : (S)0;  // row q of R (row-major block)
+        else base[j] = ((const S *)pl->prow[Q & 1])[j];
     }
     const S ss = f[Q], alpha = base[Q];
     S tau = 0, beta = alpha, scal = 1;
@@ -133,7 +133,7 @@ LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *
             const S wj = tau * d[j];
 #pragma unroll
             for (int u = 0; u < RPT; ++u) P[u][j] -= vq[u] * wj;
-            if (TS && tid == j) { pend_i = j * IB + Q; pend_v = base[j] - wj; }
+            if (TS && tid == j) { pend_i = Q * IB + j; pend_v = base[j] - wj; }
         }
     }
     // T(0:q, q) = -tau T(0:q, 0:q) G(0:q, q), with G(p, q) = v_p^T v_q = d[p]
@@ -398,15 +398,15 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
             panel_trailing<NB, PP, false>(Akk, nullptr, b, Ys, Ts);
         } else {
             S *Aik = At + c.toff(i, k);
-            for (int e = tid; e < IB * IB; e += WG) {
-                const int p = e % IB, q = e / IB;
+            for (int e = tid; e < IB * IB; e += WG) {  // Rb row-major: Rb[p*IB + q] = R(p, q)
+                const int p = e / IB, q = e % IB;
                 Rb[e] = p <= q ? Akk[(c0 + p) + (c0 + q) * NB] : (S)0;
             }
             __syncthreads();
             panel_qr<NB, S, true>(Aik, c0, Rb, Ys, Ts, pl);
             for (int e = tid; e < IB * IB; e += WG) {
                 const int p = e % IB, q = e / IB;
-                if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[e];
+                if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[p * IB + q];
                 Ti[(c0 + p) + (c0 + q) * NB] = Ts[e];
             }
             panel_trailing<NB, PP, true>(Aik, Akk, b, Ys, Ts);
