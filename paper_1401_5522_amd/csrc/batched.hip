@@ -204,7 +204,7 @@ LQ_DEV void bsys_factor(const BArgs &a, const BSys &S, char *lds, int8_t *dec_ou
     char *msm = lds + B_MMA;
     double *red = (double *)(lds + B_RED);
     float *Ys = (float *)(lds + B_QR);
-    float *Ts = Ys + IB * (NB + 1);
+    float *Ts = Ys + qr_vblk<NB>();
     float *Rb = Ts + IB * IB;
     PanelLds *pl = (PanelLds *)(Rb + IB * IB);
     __shared__ int perm_l[B_NBMAX], ipiv_l[B_NBMAX];

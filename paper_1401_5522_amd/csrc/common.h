@@ -13,7 +13,7 @@
 namespace lq {
 
 constexpr int WG = 256;    // threads per workgroup
-constexpr int IB = 32;     // inner block of panel factorizations and compact-WY factors
+constexpr int IB = 16;     // inner block of panel factorizations and compact-WY factors
 constexpr int WAVE = 64;
 
 enum Prec { P64 = 0, P32 = 1, PB16 = 2 };

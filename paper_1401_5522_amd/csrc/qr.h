@@ -10,11 +10,15 @@
 //   the other workgroups (consumers): one 64-column strip of one trailing
 //     tile column j; UNMQR on the strip of A_kj, then TSMQR(i) on the strips of
 //     (A_kj, A_ij), block reflector by block reflector as each is published.
-// A consumer keeps both strips in MFMA accumulator registers (each wave owns
-// 16 columns over all nb rows) for the whole chain, so A_kj never leaves the
-// chip between the n-k-1 updates it receives.
+// A consumer keeps the strip of A_ij in MFMA accumulator registers (each wave
+// owns 16 columns over all nb rows) and the strip of A_kj in LDS (or, where
+// LDS is short, in place in global memory) for the whole chain, so A_kj never
+// leaves the chip between the n-k-1 updates it receives.
+// The panel work of one unit grows with IB^2 (IB columns, each reducing over
+// IB columns) while the chain gains one unit per block, so IB = 16 keeps the
+// producer wavefront short.
 // Reflectors use the LAPACK convention: beta = -sign(alpha)||x||, tau = 0
-// when the tail is zero.  The QR step builds the compact-WY factor per IB = 32
+// when the tail is zero.  The QR step builds the compact-WY factor per IB
 // columns: block b of T(i,k) is the diagonal block (b*IB.., b*IB..) of the
 // nb x nb factor of tile (i,k); k_qr_gram and k_qr_tfull fill the blocks above
 // the diagonal afterwards, so the solve can apply each tile's reflectors as
@@ -48,6 +52,21 @@ template <int NB> constexpr int qr_rpt() { return NB > 256 ? 2 : 1; }  // panel 
 // (partial sums ping-pong between two LDS buffers).
 // On return Ys holds V (explicit zeros/ones for GEQRT) and Ts holds T.
 // ---------------------------------------------------------------------------
+// A block reflector V (nb x IB) staged in LDS is kept twice: column-major
+// (Yc[q*LDY + r], the operand of W = V^T C) and row-major (Yr[r*LDQ + q], the
+// operand of C -= V W).  With LDY = nb+4 and LDQ = IB+4 the sixteen lanes of
+// each quarter-wave read sixteen disjoint 16-byte bank groups, so both MFMA
+// operands load as conflict-free 128-bit reads.  vblk = both copies.
+template <int NB> constexpr int qr_ldy() { return NB + 4; }
+constexpr int LDQ = IB + 4;
+template <int NB> constexpr int qr_vblk() { return IB * qr_ldy<NB>() + NB * LDQ; }
+template <int NB, class S> LQ_DEV S *vrow(S *Ys) { return Ys + IB * qr_ldy<NB>(); }
+template <int NB, class S> LQ_DEV const S *vrow(const S *Ys) { return Ys + IB * qr_ldy<NB>(); }
+template <int NB, class S> LQ_DEV void put_v(S *Ys, int r, int q, S v) {
+    Ys[q * qr_ldy<NB>() + r] = v;
+    vrow<NB>(Ys)[r * LDQ + q] = v;
+}
+
 struct PanelLds {
     double red[2][IB * 4];  // [buffer][j][wave], holding values of the storage type S
     double prow[2][IB];     // GEQRT: pivot row of the column being reduced (type S)
@@ -71,7 +90,7 @@ LQ_DEV void qr_reduce(S (&P)[qr_rpt<NB>()][IB], int c0, PanelLds *pl) {
         }
     }
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
+    for (int half = 0; half < IB / 16; ++half) {
         S part[16];
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
@@ -169,7 +188,6 @@ LQ_DEV void qr_columns(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds 
 template <int NB, class S, bool TS>
 LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
     constexpr int RPT = qr_rpt<NB>();
-    constexpr int LDY = NB + 1;
     const int tid = threadIdx.x;
     S P[RPT][IB];
 #pragma unroll
@@ -191,7 +209,7 @@ LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
             S v;
             if (TS) v = P[u][q];
             else v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : P[u][q]);
-            Ys[q * LDY + r] = v;
+            put_v<NB>(Ys, r, q, v);
         }
     }
     __syncthreads();
@@ -201,40 +219,70 @@ LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
 // Consumer: apply one block reflector (I - V T V^T)^T to a wave's 16-column
 // slice.  `bot` holds all nb rows of the slice being eliminated into, in MFMA
 // accumulator layout; when HAS_TOP, `top` points at the eliminator row tile's
-// column for this lane (element of row r at top[r]) and only its rows
-// [c0, c0+IB) take part (TS structure: V = [E; Y]); they are read and written
-// in place.  Without HAS_TOP the reflector lives entirely in `bot`'s rows
-// (UNMQR; V given explicitly).  Ys[q*LDY + r] = Y(r, q), Ts[q*IB + p] = T(p, q).
+// column for this lane (element of row r at top[r], in global memory or LDS)
+// and only its rows [c0, c0+IB) take part (TS structure: V = [E; Y]); they
+// are read and written in place.  Without HAS_TOP the reflector lives
+// entirely in `bot`'s rows (UNMQR; V given explicitly).
+// Ys holds both LDS copies of V (put_v), Ts[q*IB + p] = T(p, q).
+// Each phase loads all of its V operands before its MFMAs (128-bit reads
+// for 4-byte storage).  W = V^T bot accumulates in two independent chains
+// (even and odd row blocks); the top rows are added afterwards.
 // ---------------------------------------------------------------------------
 template <int NB, int P, bool HAS_TOP>
 LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *top, int b,
                         const typename Tr<P>::S *Ys, const typename Tr<P>::S *Ts) {
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
-    constexpr int LDY = NB + 1;
+    constexpr int LDY = qr_ldy<NB>();
     constexpr int P2 = (P == P64) ? P64 : P32;  // precision of the small T^T W product
+    constexpr int NQ = IB / 16;                 // 16-reflector groups of the block
+    constexpr int RB = NB / 16;
+    static_assert(NQ == 1 || NQ == 2, "IB is 16 or 32");
     const int l = lane_id(), g = l >> 4, i16 = l & 15;
-    acc_t Wb[2];
+    const S *Yc = Ys, *Yr = vrow<NB>(Ys);
+    S tv[NQ][4];
     if constexpr (HAS_TOP) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < NQ; ++h)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Wb[h][r] = top[32 * b + 16 * h + Tr<P>::drow(g, r)];
-    } else {
-        Wb[0] = zero_acc<acc_t>();
-        Wb[1] = zero_acc<acc_t>();
+            for (int r = 0; r < 4; ++r) tv[h][r] = top[IB * b + 16 * h + Tr<P>::drow(g, r)];
     }
-    // W += Y^T bot
-    if constexpr (P != PB16) {
+    acc_t Wc[2][NQ];
 #pragma unroll
-        for (int rb = 0; rb < NB / 16; ++rb)
+    for (int h = 0; h < NQ; ++h) Wc[0][h] = Wc[1][h] = zero_acc<acc_t>();
+    // FP32: every V operand of both phases is read before the first MFMA
+    //   va: W phase, lane (i16, g) needs V(16 rb + drow(g, r), 16 qb + i16);
+    //   ua: update phase, V(16 rb + i16, 16 ob + drow(g, r)).
+    f4 va[NQ][RB], ua[NQ][RB];
+    if constexpr (P == P32) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * rb + Tr<P>::drow(g, r);
+        for (int qb = 0; qb < NQ; ++qb)
 #pragma unroll
-                for (int qb = 0; qb < 2; ++qb)
-                    Wb[qb] = Tr<P>::mma(Ys[(16 * qb + i16) * LDY + row], bot[rb][r], Wb[qb]);
-            }
+            for (int rb = 0; rb < RB; ++rb) va[qb][rb] = *(const f4 *)&Yc[(16 * qb + i16) * LDY + 16 * rb + 4 * g];
+#pragma unroll
+        for (int ob = 0; ob < NQ; ++ob)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) ua[ob][rb] = *(const f4 *)&Yr[(16 * rb + i16) * LDQ + 16 * ob + 4 * g];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // W += V^T bot
+    if constexpr (P == P32) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int qb = 0; qb < NQ; ++qb)
+                    Wc[rb & 1][qb] = Tr<P>::mma(va[qb][rb][r], bot[rb][r], Wc[rb & 1][qb]);
+    } else if constexpr (P == P64) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int qb = 0; qb < NQ; ++qb)
+                    Wc[rb & 1][qb] = Tr<P>::mma(Yc[(16 * qb + i16) * LDY + 16 * rb + Tr<P>::drow(g, r)], bot[rb][r],
+                                                Wc[rb & 1][qb]);
     } else {
 #pragma unroll
         for (int pr = 0; pr < NB / 32; ++pr) {
@@ -242,88 +290,130 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *
 #pragma unroll
             for (int e = 0; e < 8; ++e) bo[e] = (__bf16)bot[2 * pr + (e >> 2)][e & 3];
 #pragma unroll
-            for (int qb = 0; qb < 2; ++qb) {
+            for (int qb = 0; qb < NQ; ++qb) {
+                const f4 lo = *(const f4 *)&Yc[(16 * qb + i16) * LDY + 32 * pr + 4 * g];
+                const f4 hi = *(const f4 *)&Yc[(16 * qb + i16) * LDY + 32 * pr + 16 + 4 * g];
                 bf8 a;
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    a[e] = (__bf16)Ys[(16 * qb + i16) * LDY + 32 * pr + 16 * (e >> 2) + Tr<P>::drow(g, e & 3)];
-                Wb[qb] = Tr<PB16>::mma(a, bo, Wb[qb]);
+                for (int e = 0; e < 4; ++e) {
+                    a[e] = (__bf16)lo[e];
+                    a[4 + e] = (__bf16)hi[e];
+                }
+                Wc[pr & 1][qb] = Tr<PB16>::mma(a, bo, Wc[pr & 1][qb]);
             }
         }
     }
-    // W' = T^T W
-    acc_t Wp[2] = {zero_acc<acc_t>(), zero_acc<acc_t>()};
+    acc_t Wb[NQ];
 #pragma unroll
-    for (int qb = 0; qb < 2; ++qb)
+    for (int h = 0; h < NQ; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Wb[h][r] = Wc[0][h][r] + Wc[1][h][r];
+            if constexpr (HAS_TOP) Wb[h][r] += tv[h][r];
+        }
+    // W' = T^T W
+    acc_t Wp[NQ];
+#pragma unroll
+    for (int ob = 0; ob < NQ; ++ob) Wp[ob] = zero_acc<acc_t>();
+#pragma unroll
+    for (int qb = 0; qb < NQ; ++qb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int ob = 0; ob < 2; ++ob)
+            for (int ob = 0; ob < NQ; ++ob)
                 Wp[ob] = Tr<P2>::mma(Ts[(16 * ob + i16) * IB + 16 * qb + Tr<P>::drow(g, r)], Wb[qb][r], Wp[ob]);
     if constexpr (HAS_TOP) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < NQ; ++h)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                S *t = &top[32 * b + 16 * h + Tr<P>::drow(g, r)];
-                *t = (S)(*t - Wp[h][r]);
-            }
+            for (int r = 0; r < 4; ++r) top[IB * b + 16 * h + Tr<P>::drow(g, r)] = (S)(tv[h][r] - Wp[h][r]);
     }
-    // bot -= Y W'
-    if constexpr (P != PB16) {
+    // bot -= V W'
+    if constexpr (P == P32) {
 #pragma unroll
-        for (int rb = 0; rb < NB / 16; ++rb)
+        for (int ob = 0; ob < NQ; ++ob)
 #pragma unroll
-            for (int ob = 0; ob < 2; ++ob)
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    bot[rb] = Tr<P>::mma(-Ys[(16 * ob + Tr<P>::drow(g, r)) * LDY + 16 * rb + i16], Wp[ob][r], bot[rb]);
+                for (int rb = 0; rb < RB; ++rb) bot[rb] = Tr<P>::mma(-ua[ob][rb][r], Wp[ob][r], bot[rb]);
+    } else if constexpr (P == P64) {
+#pragma unroll
+        for (int ob = 0; ob < NQ; ++ob)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    bot[rb] = Tr<P>::mma(-Yr[(16 * rb + i16) * LDQ + 16 * ob + Tr<P>::drow(g, r)], Wp[ob][r], bot[rb]);
     } else {
+        // K = 32 per MFMA; a 16-reflector block fills the second half with zeros
         bf8 bw;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bw[e] = (__bf16)Wp[e >> 2][e & 3];
+        for (int e = 0; e < 8; ++e) bw[e] = (e >> 2) < NQ ? (__bf16)Wp[(e >> 2) % NQ][e & 3] : (__bf16)0.0f;
 #pragma unroll
-        for (int rb = 0; rb < NB / 16; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
             bf8 a;
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                a[e] = (__bf16)(-Ys[(16 * (e >> 2) + Tr<P>::drow(g, e & 3)) * LDY + 16 * rb + i16]);
+            for (int h = 0; h < 2; ++h) {
+                f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (h < NQ) v = *(const f4 *)&Yr[(16 * rb + i16) * LDQ + 16 * h + 4 * g];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[4 * h + e] = (__bf16)(-v[e]);
+            }
             bot[rb] = Tr<PB16>::mma(a, bw, bot[rb]);
         }
     }
 }
 
-// Stage block reflector b of tile V (column block c0 = b*IB) and its T block
-// into LDS for apply_block: Ys[q*LDY + r] = V(r, c0+q), Ts[q*IB + p] = T(p, q).
-// GEQRT = true makes V unit-lower explicit (zeros above, ones on the
-// diagonal).  Every thread issues all of its loads before the first store.
+// Staging of block reflector b of tile V (column block c0 = b*IB) and its T
+// block for apply_block, in two halves so that the global loads of the next
+// block can be in flight while the current one is applied:
+//   stage_load:  V(:, c0..c0+IB) and T(c0.., c0..) into registers;
+//   stage_store: into LDS, both copies of V(:, c0..c0+IB) and Ts[q*IB + p] = T(p, q);
+//                GEQRT = true makes V unit-lower explicit (zeros above, ones on
+//                the diagonal).
+template <int NB, class S> struct StageRegs {
+    static constexpr int PY = NB * IB / WG, PT = IB * IB / WG;
+    static_assert(PY * WG == NB * IB && PT * WG == IB * IB, "whole elements per thread");
+    S y[PY], t[PT];
+};
+
+template <int NB, class S>
+LQ_DEV void stage_load(const S *V, const S *T, int c0, StageRegs<NB, S> &sr) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < StageRegs<NB, S>::PY; ++u) {
+        const int e = tid + WG * u, r = e % NB, q = e / NB;
+        sr.y[u] = V[r + (size_t)(c0 + q) * NB];
+    }
+#pragma unroll
+    for (int u = 0; u < StageRegs<NB, S>::PT; ++u) {
+        const int e = tid + WG * u;
+        sr.t[u] = T[(c0 + e % IB) + (size_t)(c0 + e / IB) * NB];
+    }
+}
+
+template <int NB, class S, bool GEQRT>
+LQ_DEV void stage_store(const StageRegs<NB, S> &sr, int c0, S *Ys, S *Ts) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < StageRegs<NB, S>::PY; ++u) {
+        const int e = tid + WG * u, r = e % NB, q = e / NB;
+        S v = sr.y[u];
+        if (GEQRT) v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : v);
+        put_v<NB>(Ys, r, q, v);
+    }
+#pragma unroll
+    for (int u = 0; u < StageRegs<NB, S>::PT; ++u) {
+        const int e = tid + WG * u;
+        Ts[(e / IB) * IB + e % IB] = sr.t[u];
+    }
+}
+
 template <int NB, class S, bool GEQRT>
 LQ_DEV void stage_block(const S *V, const S *T, int c0, S *Ys, S *Ts) {
-    constexpr int LDY = NB + 1, PY = NB * IB / WG, PT = IB * IB / WG;
-    const int tid = threadIdx.x;
-    S y[PY], t[PT];
-#pragma unroll
-    for (int u = 0; u < PY; ++u) {
-        const int e = tid + WG * u, r = e % NB, q = e / NB;
-        y[u] = V[r + (size_t)(c0 + q) * NB];
-    }
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-        const int e = tid + WG * u;
-        t[u] = T[(c0 + e % IB) + (size_t)(c0 + e / IB) * NB];
-    }
-#pragma unroll
-    for (int u = 0; u < PY; ++u) {
-        const int e = tid + WG * u, r = e % NB, q = e / NB;
-        S v = y[u];
-        if (GEQRT) v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : v);
-        Ys[q * LDY + r] = v;
-    }
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-        const int e = tid + WG * u;
-        Ts[(e / IB) * IB + e % IB] = t[u];
-    }
+    StageRegs<NB, S> sr;
+    stage_load<NB, S>(V, T, c0, sr);
+    stage_store<NB, S, GEQRT>(sr, c0, Ys, Ts);
 }
 
 // Trailing update of a producer panel: columns (b+1)*IB..NB-1 of A (and, for
@@ -356,7 +446,7 @@ LQ_DEV void panel_trailing(typename Tr<P>::S *A, typename Tr<P>::S *R, int b, co
 }
 
 template <int NB, int P> constexpr int qr_lds() {
-    return (IB * (NB + 1) + 2 * IB * IB) * (int)sizeof(typename Tr<P>::S) + (int)sizeof(PanelLds);
+    return (qr_vblk<NB>() + 2 * IB * IB) * (int)sizeof(typename Tr<P>::S) + (int)sizeof(PanelLds);
 }
 
 // Strips of 64 columns (16 per wave); for nb = 32 one strip with two active waves.
@@ -372,9 +462,8 @@ template <int NB, int P>
 LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
     typedef typename Tr<P>::S S;
     constexpr int PP = (P == PB16) ? P32 : P;  // panel-internal updates stay in the storage precision
-    constexpr int LDY = NB + 1;
     S *Ys = (S *)smem;
-    S *Ts = Ys + IB * LDY;
+    S *Ts = Ys + qr_vblk<NB>();
     S *Rb = Ts + IB * IB;
     PanelLds *pl = (PanelLds *)(Rb + IB * IB);
     __shared__ int bail;
@@ -417,17 +506,43 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
     }
 }
 
+// Consumer LDS: two staging buffers (block s is applied from one while block
+// s+1 is written into the other) and, for 4-byte storage with nb <= 256, the
+// eliminator row strip A_kj (64 columns x nb rows) for the whole chain.
+template <int NB> constexpr int qr_ldt() { return NB + 4; }  // column stride of the LDS strip
+template <int NB, int P> constexpr int qr_stage_lds() {
+    return 2 * (qr_vblk<NB>() + IB * IB) * (int)sizeof(typename Tr<P>::S);
+}
+template <int NB, int P> constexpr bool qr_top_lds() {
+    return sizeof(typename Tr<P>::S) == 4 && qr_stage_lds<NB, P>() + 64 * qr_ldt<NB>() * 4 <= 150 * 1024;
+}
+template <int NB, int P> constexpr int qr_cons_lds() {
+    return qr_stage_lds<NB, P>() + (qr_top_lds<NB, P>() ? 64 * qr_ldt<NB>() * 4 : 0);
+}
+template <int NB, int P> constexpr int qr_step_lds() {
+    return qr_lds<NB, P>() > qr_cons_lds<NB, P>() ? qr_lds<NB, P>() : qr_cons_lds<NB, P>();
+}
+
 template <int NB, int P>
 __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
     if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
-    constexpr int LDY = NB + 1;
-    __shared__ __attribute__((aligned(16))) char smem[qr_lds<NB, P>()];
+    constexpr int LDT = qr_ldt<NB>(), VB = qr_vblk<NB>();
+    constexpr int NBLK = NB / IB;
+    constexpr bool TLDS = qr_top_lds<NB, P>();
+    __shared__ __attribute__((aligned(16))) char smem[qr_step_lds<NB, P>()];
     if ((int)blockIdx.x < qr_pw<NB>()) {
         qr_producer<NB, P>(c, k, (int)blockIdx.x, smem);
         return;
     }
+    // Consumer: one 64-column strip of trailing tile column j.  The blocks it
+    // applies form one sequence s = 0 .. (n-k)*NBLK-1: block b of tile i =
+    // k + s/NBLK, first the UNMQR blocks of the GEQRT tile (i = k) on A_kj,
+    // then the TSMQR blocks of every A_ik on (A_kj, A_ij).  Block s+1 is
+    // loaded into registers before block s is applied and stored into the
+    // other LDS buffer afterwards, so each block costs one barrier; the flag
+    // of block s+2 is read early and waited on only if it was not yet set.
     S *At = (S *)c.At;
     S *Tf = (S *)c.Tf;
     const int epoch = k + 1;
@@ -436,70 +551,97 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
     const int j = k + 1 + strip / qr_spc<NB>();
     const int col0 = (strip % qr_spc<NB>()) * 64 + 16 * w;
     const bool active = col0 < NB;
-    S *Ys = (S *)smem;
-    S *Ts = Ys + IB * LDY;
-    acc_t bot[NB / 16];
-    S *Akj = At + c.toff(k, j);
-    S *topc = Akj + (col0 + (l & 15)) * NB;  // this lane's column of the eliminator row tile
     const int g = l >> 4, i16 = l & 15;
-    __shared__ int bail;
-    {  // UNMQR on the strip of A_kj: explicit V blocks of the GEQRT tile
-        const S *V = At + c.toff(k, k);
-        const S *T = Tf + c.tqoff(k, k);
-        if (active) {
+    S *const Y0 = (S *)smem;          // staging buffer u: V at Y0 + u*VB, T at T0 + u*IB*IB
+    S *const T0 = Y0 + 2 * VB;
+    float *Tops = (float *)(T0 + 2 * IB * IB);  // TLDS only: column c of the strip at Tops[c*LDT]
+    __shared__ int bail[2];
+    S *Akj = At + c.toff(k, j);
+    S *topc;  // this lane's column of A_kj for the TSMQR blocks
+    if constexpr (TLDS) topc = (S *)(Tops + (16 * w + i16) * LDT);
+    else topc = Akj + (col0 + i16) * NB;
+    const int nblocks = (c.n - k) * NBLK;
+    auto vtile = [&](int s) { return At + c.toff(k + s / NBLK, k); };
+    auto ttile = [&](int s) { return Tf + c.tqoff(k + s / NBLK, k); };
+    auto flag_of = [&](int s) { return qr_flag(c, k + s / NBLK, s % NBLK); };
+    acc_t bot[NB / 16];
+    auto load_bot = [&](const S *src) {
 #pragma unroll
-            for (int rb = 0; rb < NB / 16; ++rb)
+        for (int rb = 0; rb < NB / 16; ++rb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) bot[rb][r] = Akj[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB];
-        }
-        for (int b = 0; b < NB / IB; ++b) {
-            const int c0 = b * IB;
-            if (tid == 0) bail = !flag_wait(qr_flag(c, k, b), epoch, &c.st->watchdog);
-            __syncthreads();
-            if (bail) return;
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
-            stage_block<NB, S, true>(V, T, c0, Ys, Ts);
-            __syncthreads();
-            if (active) apply_block<NB, P, false>(bot, nullptr, b, Ys, Ts);
-            __syncthreads();
-        }
-        if (active) {
+            for (int r = 0; r < 4; ++r) bot[rb][r] = src[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB];
+    };
+    auto store_bot = [&](S *dst) {
 #pragma unroll
-            for (int rb = 0; rb < NB / 16; ++rb)
+        for (int rb = 0; rb < NB / 16; ++rb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Akj[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB] = (S)bot[rb][r];
-        }
+            for (int r = 0; r < 4; ++r) dst[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB] = (S)bot[rb][r];
+    };
+    // prologue: block 0 staged, flag of block 1 awaited
+    if (tid == 0) {
+        bail[0] = !flag_wait(flag_of(0), epoch, &c.st->watchdog);
+        bail[1] = nblocks > 1 ? !flag_wait(flag_of(1), epoch, &c.st->watchdog) : 0;
     }
-    for (int i = k + 1; i < c.n; ++i) {
-        S *Aij = At + c.toff(i, j);
-        const S *Y = At + c.toff(i, k);
-        const S *T = Tf + c.tqoff(i, k);
-        if (active) {
-#pragma unroll
-            for (int rb = 0; rb < NB / 16; ++rb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) bot[rb][r] = Aij[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB];
-        }
-        for (int b = 0; b < NB / IB; ++b) {
-            const int c0 = b * IB;
-            if (tid == 0) bail = !flag_wait(qr_flag(c, i, b), epoch, &c.st->watchdog);
-            __syncthreads();
-            if (bail) return;
+    __syncthreads();
+    if (bail[0] || bail[1]) return;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    if (active) load_bot(Akj);
+    stage_block<NB, S, true>(vtile(0), ttile(0), 0, Y0, T0);
+    __syncthreads();
+    for (int s = 0; s < nblocks; ++s) {
+        const int cur = s & 1;
+        const bool has_next = s + 1 < nblocks;
+        if (has_next && bail[(s + 1) & 1]) return;  // the flag of block s+1 was never set
+        const int i = k + s / NBLK, b = s % NBLK;
+        StageRegs<NB, S> nx;
+        if (has_next) {
             __atomic_thread_fence(__ATOMIC_ACQUIRE);
-            stage_block<NB, S, false>(Y, T, c0, Ys, Ts);
-            __syncthreads();
-            if (active) apply_block<NB, P, true>(bot, topc, b, Ys, Ts);
-            __syncthreads();
+            stage_load<NB, S>(vtile(s + 1), ttile(s + 1), ((s + 1) % NBLK) * IB, nx);
         }
+        // every lane reads the flag (one cache line per wave, no branch), so the
+        // value is waited for only where thread 0 tests it after the apply
+        const int fv = __hip_atomic_load(flag_of(s + 2 < nblocks ? s + 2 : s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (active) {
+            const S *Yc = Y0 + cur * VB, *Tc = T0 + cur * (IB * IB);
+            if (i == k) apply_block<NB, P, false>(bot, nullptr, b, Yc, Tc);
+            else apply_block<NB, P, true>(bot, topc, b, Yc, Tc);
+            if (b == NBLK - 1) {  // tile i done: hand A_kj to the LDS strip, or write A_ij back
+                if (i == k) {
+                    if constexpr (TLDS) {
+#pragma unroll
+                        for (int rb = 0; rb < NB / 16; ++rb)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) topc[16 * rb + Tr<P>::drow(g, r)] = (S)bot[rb][r];
+                    } else {
+                        store_bot(Akj);
+                    }
+                } else {
+                    store_bot(At + c.toff(i, j));
+                }
+                if (i + 1 < c.n) load_bot(At + c.toff(i + 1, j));
+            }
+        }
+        if (has_next) {
+            S *Yn = Y0 + (cur ^ 1) * VB, *Tn = T0 + (cur ^ 1) * (IB * IB);
+            if ((s + 1) / NBLK == 0) stage_store<NB, S, true>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
+            else stage_store<NB, S, false>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
+        }
+        if (tid == 0 && s + 2 < nblocks)
+            bail[s & 1] = fv >= epoch ? 0 : !flag_wait(flag_of(s + 2), epoch, &c.st->watchdog);
+        __syncthreads();
+    }
+    if constexpr (TLDS) {  // the finished rows of A_kj
         if (active) {
 #pragma unroll
             for (int rb = 0; rb < NB / 16; ++rb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Aij[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB] = (S)bot[rb][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * rb + Tr<P>::drow(g, r);
+                    Akj[row + (col0 + i16) * NB] = topc[row];
+                }
         }
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // Completion of the nb x nb compact-WY factors of a QR step's panel tiles
@@ -512,18 +654,26 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
 // not overlap, so V(:,0:c)^T V(:,c:) = Y(:,0:c)^T Y(:,c:); for the GEQRT tile
 // V is the unit-lower part of the factored diagonal tile.
 // ---------------------------------------------------------------------------
-template <int NB> constexpr int qr_npairs() { return (NB / IB) * (NB / IB - 1) / 2; }
+// The Gram matrix is formed in GB x GB blocks (GB = 32, the smallest tile of
+// the four-wave MFMA routine): every block (a, b) with a < b, and with IB < GB
+// also the diagonal blocks, whose upper off-diagonal IB-blocks the recurrence
+// reads.
+constexpr int GB = 32;
+static_assert(GB % IB == 0, "IB divides the Gram block");
+template <int NB> constexpr int qr_npairs() {
+    return IB < GB ? (NB / GB) * (NB / GB + 1) / 2 : (NB / GB) * (NB / GB - 1) / 2;
+}
 
-// Gram blocks G(a, b) = V_a^T V_b, a < b, in FP64 (MFMA), one IB x IB block per
+// Gram blocks G(a, b) = V_a^T V_b in FP64 (MFMA), one GB x GB block per
 // workgroup; grid (pairs, n-k).
 template <int NB, int P>
 __global__ __launch_bounds__(WG) void k_qr_gram(Ctx c, int k) {
     if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
-    __shared__ __attribute__((aligned(16))) char smem[mma_lds_bytes<P64, IB, IB, 16>()];
-    int p = blockIdx.x, bb = 1;
-    while (p >= bb) { p -= bb; ++bb; }
-    const int a0 = p * IB, b0 = bb * IB;
+    __shared__ __attribute__((aligned(16))) char smem[mma_lds_bytes<P64, GB, GB, 16>()];
+    int p = blockIdx.x, bb = IB < GB ? 0 : 1;  // column block bb holds pairs p = 0..bb (or 0..bb-1)
+    while (p >= bb + (IB < GB)) { p -= bb + (IB < GB); ++bb; }
+    const int a0 = p * GB, b0 = bb * GB;
     const int t = blockIdx.y, i = k + t;
     const S *V = (const S *)c.At + c.toff(i, k);
     const bool ts = i > k;
@@ -532,11 +682,11 @@ __global__ __launch_bounds__(WG) void k_qr_gram(Ctx c, int k) {
         return r < col ? 0.0 : (r == col ? 1.0 : (double)V[r + (size_t)col * NB]);
     };
     Tr<P64>::acc acc[1][1];
-    acc_zero<P64, IB, IB, 2, 2>(acc);
-    wg_mma<P64, IB, IB, 2, 2, 16>(
+    acc_zero<P64, GB, GB, 2, 2>(acc);
+    wg_mma<P64, GB, GB, 2, 2, 16>(
         acc, NB, [&](int r, int kk) { return v(kk, a0 + r); }, [&](int kk, int cc) { return v(kk, b0 + cc); }, smem);
     double *G = c.gram + (size_t)t * NB * NB;
-    acc_foreach<P64, IB, IB, 2, 2>(acc, [&](int r, int cc, double x) { G[(a0 + r) + (size_t)(b0 + cc) * NB] = x; });
+    acc_foreach<P64, GB, GB, 2, 2>(acc, [&](int r, int cc, double x) { G[(a0 + r) + (size_t)(b0 + cc) * NB] = x; });
 }
 
 // Off-diagonal blocks of T, block column by block column; one workgroup per
@@ -545,7 +695,8 @@ template <int NB, int P>
 __global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k) {
     if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
-    constexpr int MR = (NB - IB) / 8;  // rows a per thread at most
+    constexpr int AS = WG / IB;        // row stride: thread tid takes rows tid/IB + AS m
+    constexpr int MR = (NB - IB) / AS;  // rows a per thread at most
     __shared__ double Gs[(NB - IB) * IB];  // G(0:c, c:c+IB), then Y1 = T(0:c,0:c) G(...)
     __shared__ double Tb[IB * IB];
     const int t = blockIdx.x, i = k + t;
@@ -563,7 +714,7 @@ __global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k) {
         double y1[MR];
 #pragma unroll
         for (int m = 0; m < MR; ++m) {
-            const int a = a1 + 8 * m;
+            const int a = a1 + AS * m;
             double acc = 0.0;
             if (a < c0)
                 for (int a2 = a; a2 < c0; ++a2) acc += (double)T[a + (size_t)a2 * NB] * Gs[a2 * IB + q];
@@ -572,11 +723,11 @@ __global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k) {
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < MR; ++m) {
-            const int a = a1 + 8 * m;
+            const int a = a1 + AS * m;
             if (a < c0) Gs[a * IB + q] = y1[m];
         }
         __syncthreads();
-        for (int a = a1; a < c0; a += 8) {
+        for (int a = a1; a < c0; a += AS) {
             double acc = 0.0;
             for (int pp = 0; pp <= q; ++pp) acc += Gs[a * IB + pp] * Tb[pp * IB + q];
             T[a + (size_t)(c0 + q) * NB] = (S)(-acc);
