@@ -176,8 +176,19 @@ LQ_DEV void wave_sync() {
 }
 
 // ---- cross-workgroup flags (agent scope) -----------------------------------
+// Producer and consumer workgroups of a kernel run on one device, so every
+// fence of the flag protocol is agent-scoped (a system-scope fence would also
+// write back or invalidate cache lines for host and peer coherence).
+LQ_DEV void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+LQ_DEV void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// The cache half of an agent-scope acquire: invalidate the vector caches so
+// later loads see data published by other workgroups.  For use after a
+// barrier that follows another thread's completed flag read; unlike
+// fence_acquire it does not first wait for this wave's own outstanding
+// stores (which need no ordering against the published data).
+LQ_DEV void cache_invalidate() { asm volatile("buffer_inv sc1" ::: "memory"); }
 LQ_DEV void flag_publish(int *f, int v) {
-    __atomic_thread_fence(__ATOMIC_RELEASE);  // make prior writes of this thread visible
+    fence_release();  // make prior writes of this thread visible
     __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Spin until *f >= v.  Returns false if the spin bound is exhausted.
@@ -191,7 +202,7 @@ LQ_DEV bool flag_wait(const int *f, int v, int *watchdog) {
         }
         if (__hip_atomic_load(watchdog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
     }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    fence_acquire();
     return true;
 }
 

@@ -356,7 +356,12 @@ LQ_DEV void apply_slices(typename Tr<P>::acc (&bot)[NS][NB / 16], typename Tr<P>
                 for (int r = 0; r < 4; ++r)
                     top[ns][IB * b + 16 * h + Tr<P>::drow(g, r)] = (S)(tv[ns][h][r] - Wp[ns][h][r]);
     }
-    // bot -= V W'
+    // bot -= V W', as bot += V (-W'): the sign goes on the NQ x 4 values of W'
+    // once rather than on each of the V operands
+#pragma unroll
+    for (int ns = 0; ns < NS; ++ns)
+#pragma unroll
+        for (int ob = 0; ob < NQ; ++ob) Wp[ns][ob] = -Wp[ns][ob];
     if constexpr (P == P32) {
         if constexpr (NS > 1) {
             load_ua();
@@ -370,7 +375,7 @@ LQ_DEV void apply_slices(typename Tr<P>::acc (&bot)[NS][NB / 16], typename Tr<P>
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int ns = 0; ns < NS; ++ns)
-                        bot[ns][rb] = Tr<P>::mma(-ua[ob][rb][r], Wp[ns][ob][r], bot[ns][rb]);
+                        bot[ns][rb] = Tr<P>::mma(ua[ob][rb][r], Wp[ns][ob][r], bot[ns][rb]);
     } else if constexpr (P == P64) {
 #pragma unroll
         for (int ob = 0; ob < NQ; ++ob)
@@ -378,7 +383,7 @@ LQ_DEV void apply_slices(typename Tr<P>::acc (&bot)[NS][NB / 16], typename Tr<P>
             for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
-                    const S y = -Yr[(16 * rb + i16) * LDQ + 16 * ob + Tr<P>::drow(g, r)];
+                    const S y = Yr[(16 * rb + i16) * LDQ + 16 * ob + Tr<P>::drow(g, r)];
 #pragma unroll
                     for (int ns = 0; ns < NS; ++ns) bot[ns][rb] = Tr<P>::mma(y, Wp[ns][ob][r], bot[ns][rb]);
                 }
@@ -398,7 +403,7 @@ LQ_DEV void apply_slices(typename Tr<P>::acc (&bot)[NS][NB / 16], typename Tr<P>
                 f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
                 if (h < NQ) v = *(const f4 *)&Yr[(16 * rb + i16) * LDQ + 16 * h + 4 * g];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) a[4 * h + e] = (__bf16)(-v[e]);
+                for (int e = 0; e < 4; ++e) a[4 * h + e] = (__bf16)v[e];
             }
 #pragma unroll
             for (int ns = 0; ns < NS; ++ns) bot[ns][rb] = Tr<PB16>::mma(a, bw[ns], bot[ns][rb]);
@@ -531,7 +536,7 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
             if (tid == 0) bail = !flag_wait(qr_flag(c, i, b - 1), epoch, &c.st->watchdog);
             __syncthreads();
             if (bail) return;
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            fence_acquire();
         }
         S *Ti = Tf + c.tqoff(i, k);
         if (i == k) {
@@ -553,7 +558,7 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
             }
             panel_trailing<NB, PP, true>(Aik, Akk, b, Ys, Ts);
         }
-        __threadfence();
+        fence_release();  // every thread's writes of unit (i, b) before the flag
         __syncthreads();
         if (tid == 0) flag_publish(qr_flag(c, i, b), epoch);
     }
@@ -597,8 +602,14 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
     // k + s/NBLK, first the UNMQR blocks of the GEQRT tile (i = k) on A_kj,
     // then the TSMQR blocks of every A_ik on (A_kj, A_ij).  Block s+1 is
     // loaded into registers before block s is applied and stored into the
-    // other LDS buffer afterwards, so each block costs one barrier; the flag
-    // of block s+2 is read early and waited on only if it was not yet set.
+    // other LDS buffer afterwards, so each block costs one barrier.
+    // Cache invalidation is the expensive half of acquiring a block (several
+    // microseconds per wave), so one invalidation covers every block whose
+    // flag was seen set before it: the wavefront order of the producers makes
+    // flag (i', b') imply all flags (i <= i', b <= b'), so when the flag of
+    // the last block of a tile is already set the whole tile is covered.
+    // Thread 0 keeps the index `covered` up to which blocks are acquired; the
+    // flag that would extend it is read early and waited on only if unset.
     S *At = (S *)c.At;
     S *Tf = (S *)c.Tf;
     const int epoch = k + 1;
@@ -611,7 +622,7 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
     S *const Y0 = (S *)smem;          // staging buffer u: V at Y0 + u*VB, T at T0 + u*IB*IB
     S *const T0 = Y0 + 2 * VB;
     float *Tops = (float *)(T0 + 2 * IB * IB);  // TLDS only: column c of the strip at Tops[c*LDT]
-    __shared__ int bail[2];
+    __shared__ int bail[2], inval[2];  // for block x: slot x & 1
     S *Akj = At + c.toff(k, j);
     S *topc[NS];  // this lane's columns of A_kj for the TSMQR blocks
 #pragma unroll
@@ -642,14 +653,19 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
                 for (int r = 0; r < 4; ++r)
                     dst[(16 * rb + Tr<P>::drow(g, r)) + (col0 + 64 * ns + i16) * NB] = (S)bot[ns][rb][r];
     };
-    // prologue: block 0 staged, flag of block 1 awaited
+    auto tile_end = [&](int s) { return (s / NBLK) * NBLK + NBLK - 1; };
+    int covered = 1;  // thread 0: blocks 0..covered are acquired
+    // prologue: block 0 staged, flag of block 1 awaited (nblocks >= 2 NBLK)
     if (tid == 0) {
         bail[0] = !flag_wait(flag_of(0), epoch, &c.st->watchdog);
-        bail[1] = nblocks > 1 ? !flag_wait(flag_of(1), epoch, &c.st->watchdog) : 0;
+        bail[1] = !flag_wait(flag_of(1), epoch, &c.st->watchdog);
+        if (__hip_atomic_load(flag_of(NBLK - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch)
+            covered = NBLK - 1;
+        inval[0] = inval[1] = 0;
     }
     __syncthreads();
     if (bail[0] || bail[1]) return;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    fence_acquire();
     if (active) load_bot(Akj);
     stage_block<NB, S, true>(vtile(0), ttile(0), 0, Y0, T0);
     __syncthreads();
@@ -660,12 +676,14 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
         const int i = k + s / NBLK, b = s % NBLK;
         StageRegs<NB, S> nx;
         if (has_next) {
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            if (inval[(s + 1) & 1]) cache_invalidate();
             stage_load<NB, S>(vtile(s + 1), ttile(s + 1), ((s + 1) % NBLK) * IB, nx);
         }
-        // every lane reads the flag (one cache line per wave, no branch), so the
-        // value is waited for only where thread 0 tests it after the apply
-        const int fv = __hip_atomic_load(flag_of(s + 2 < nblocks ? s + 2 : s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the flag of the last block of block s+2's tile: every lane reads it
+        // (one cache line per wave, no branch), so the value is waited for only
+        // where thread 0 tests it after the apply
+        const int fe = __hip_atomic_load(flag_of(tile_end(s + 2 < nblocks ? s + 2 : s)), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
         if (active) {
             const S *Yc = Y0 + cur * VB, *Tc = T0 + cur * (IB * IB);
             if (i == k) apply_slices<NB, P, false, NS>(bot, topc, b, Yc, Tc);
@@ -691,8 +709,20 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
             if ((s + 1) / NBLK == 0) stage_store<NB, S, true>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
             else stage_store<NB, S, false>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
         }
-        if (tid == 0 && s + 2 < nblocks)
-            bail[s & 1] = fv >= epoch ? 0 : !flag_wait(flag_of(s + 2), epoch, &c.st->watchdog);
+        if (tid == 0 && s + 2 < nblocks) {
+            int bl = 0, inv = 0;
+            if (s + 2 > covered) {
+                inv = 1;
+                if (fe >= epoch) {
+                    covered = tile_end(s + 2);
+                } else {
+                    bl = !flag_wait(flag_of(s + 2), epoch, &c.st->watchdog);
+                    covered = s + 2;
+                }
+            }
+            bail[s & 1] = bl;
+            inval[s & 1] = inv;
+        }
         __syncthreads();
     }
     if constexpr (TLDS) {  // the finished rows of A_kj
