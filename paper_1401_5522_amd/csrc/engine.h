@@ -29,9 +29,6 @@ struct Eng {
     static void factor(const Ctx &c, const Layout &L, const double *A, int64_t lda, const luqr_opts &o, int nsteps,
                        hipStream_t st, hipEvent_t *ev) {
         const int n = (int)c.n;
-        int dev = 0, ncu = 256;  // CUs: one QR-step workgroup fits per CU
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         k_status_reset<<<1, 64, 0, st>>>(c.st);
         k_fill_int<<<nblk((int64_t)n * (NB / IB)), WG, 0, st>>>(c.flags, (int64_t)n * (NB / IB), 0);
         k_fill_int<<<nblk(n), WG, 0, st>>>(c.dec, n, -1);
@@ -60,14 +57,7 @@ struct Eng {
                 k_lu_update<NB, P><<<(unsigned)rest * rest * PER * PER, WG, 0, st>>>(c, k);
             }
             if (ev) (void)hipEventRecord(ev[E * k + 3], st);
-            // two slices per wave (4-byte storage) when one workgroup per strip would not fit
-            constexpr bool CAN2 = NB >= 128 && sizeof(S) == 4;
-            bool two = false;
-            if constexpr (CAN2) two = qr_pw<NB>() + rest * qr_spc<NB>() > ncu;
-            if constexpr (CAN2) {
-                if (two) k_qr_step<NB, P, 2><<<qr_pw<NB>() + rest * qr_spc<NB, 2>(), WG, 0, st>>>(c, k);
-            }
-            if (!two) k_qr_step<NB, P, 1><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
+            k_qr_step<NB, P><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
             if (ev) (void)hipEventRecord(ev[E * k + 4], st);
             k_qr_rinv<NB, S><<<NB / 4, WG, 0, st>>>(c, k);
             if constexpr (NB > IB) {

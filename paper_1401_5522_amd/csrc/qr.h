@@ -216,22 +216,24 @@ LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
 }
 
 // ---------------------------------------------------------------------------
-// Consumer: apply one block reflector (I - V T V^T)^T to a wave's NS
-// 16-column slices (every V operand read serves all of them).  bot[ns] holds
-// all nb rows of slice ns of the tile being eliminated into, in MFMA
-// accumulator layout; when HAS_TOP, top[ns] points at the eliminator row
-// tile's column for this lane (element of row r at top[ns][r], in global
-// memory or LDS) and only its rows [c0, c0+IB) take part (TS structure: V = [E; Y]); they
+// Consumer: apply one block reflector (I - V T V^T)^T to a wave's 16-column
+// slice.  `bot` holds all nb rows of the slice of the tile being eliminated
+// into, in MFMA accumulator layout; when HAS_TOP, `top` points at the
+// eliminator row tile's column for this lane (element of row r at top[r])
+// and only its rows [c0, c0+IB) take part (TS structure: V = [E; Y]); they
 // are read and written in place.  Without HAS_TOP the reflector lives
 // entirely in `bot`'s rows (UNMQR; V given explicitly).
 // Ys holds both LDS copies of V (put_v), Ts[q*IB + p] = T(p, q).
-// Each phase loads all of its V operands before its MFMAs (128-bit reads
-// for 4-byte storage).  W = V^T bot accumulates in two independent chains
-// (even and odd row blocks); the top rows are added afterwards.
+// W = V^T bot accumulates in two independent chains (even and odd row
+// blocks); the top rows are added afterwards, so their load is off the chain.
+// PRE (one workgroup per CU): every V operand of both phases is read before
+// the first MFMA.  Otherwise (two workgroups per CU, half the registers) each
+// 128-bit operand is read just before its MFMAs and the other workgroup
+// covers the latency.
 // ---------------------------------------------------------------------------
-template <int NB, int P, bool HAS_TOP, int NS>
-LQ_DEV void apply_slices(typename Tr<P>::acc (&bot)[NS][NB / 16], typename Tr<P>::S *const (&top)[NS], int b,
-                         const typename Tr<P>::S *Ys, const typename Tr<P>::S *Ts) {
+template <int NB, int P, bool HAS_TOP, bool PRE = true>
+LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *top, int b,
+                        const typename Tr<P>::S *Ys, const typename Tr<P>::S *Ts) {
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
     constexpr int LDY = qr_ldy<NB>();
@@ -241,39 +243,31 @@ LQ_DEV void apply_slices(typename Tr<P>::acc (&bot)[NS][NB / 16], typename Tr<P>
     static_assert(NQ == 1 || NQ == 2, "IB is 16 or 32");
     const int l = lane_id(), g = l >> 4, i16 = l & 15;
     const S *Yc = Ys, *Yr = vrow<NB>(Ys);
-    S tv[NS][NQ][4];
+    // lane (i16, g) needs V(16 rb + drow(g, r), 16 qb + i16) in the W phase and
+    // V(16 rb + i16, 16 ob + drow(g, r)) in the update; for 4-byte storage
+    // (drow = 4g + r) both are one 128-bit read per (block, rb)
+    auto vw = [&](int qb, int rb) { return *(const f4 *)&Yc[(16 * qb + i16) * LDY + 16 * rb + 4 * g]; };
+    auto vu = [&](int ob, int rb) { return *(const f4 *)&Yr[(16 * rb + i16) * LDQ + 16 * ob + 4 * g]; };
+    S tv[NQ][4];
     if constexpr (HAS_TOP) {
 #pragma unroll
-        for (int ns = 0; ns < NS; ++ns)
+        for (int h = 0; h < NQ; ++h)
 #pragma unroll
-            for (int h = 0; h < NQ; ++h)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) tv[ns][h][r] = top[ns][IB * b + 16 * h + Tr<P>::drow(g, r)];
+            for (int r = 0; r < 4; ++r) tv[h][r] = top[IB * b + 16 * h + Tr<P>::drow(g, r)];
     }
-    acc_t Wc[NS][2][NQ];
+    acc_t Wc[2][NQ];
 #pragma unroll
-    for (int ns = 0; ns < NS; ++ns)
-#pragma unroll
-        for (int h = 0; h < NQ; ++h) Wc[ns][0][h] = Wc[ns][1][h] = zero_acc<acc_t>();
-    // FP32: the V operands are read before the MFMAs that use them
-    //   va: W phase, lane (i16, g) needs V(16 rb + drow(g, r), 16 qb + i16);
-    //   ua: update phase, V(16 rb + i16, 16 ob + drow(g, r)).
-    // With one slice both sets are read up front; with more, the update's set
-    // is read after W, which keeps the slices' accumulators and both sets
-    // within the register file.
+    for (int h = 0; h < NQ; ++h) Wc[0][h] = Wc[1][h] = zero_acc<acc_t>();
     f4 va[NQ][RB], ua[NQ][RB];
-    auto load_ua = [&]() {
-#pragma unroll
-        for (int ob = 0; ob < NQ; ++ob)
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) ua[ob][rb] = *(const f4 *)&Yr[(16 * rb + i16) * LDQ + 16 * ob + 4 * g];
-    };
-    if constexpr (P == P32) {
+    if constexpr (P == P32 && PRE) {
 #pragma unroll
         for (int qb = 0; qb < NQ; ++qb)
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) va[qb][rb] = *(const f4 *)&Yc[(16 * qb + i16) * LDY + 16 * rb + 4 * g];
-        if constexpr (NS == 1) load_ua();
+            for (int rb = 0; rb < RB; ++rb) va[qb][rb] = vw(qb, rb);
+#pragma unroll
+        for (int ob = 0; ob < NQ; ++ob)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) ua[ob][rb] = vu(ob, rb);
         __builtin_amdgcn_sched_barrier(0);
     }
     // W += V^T bot
@@ -281,143 +275,103 @@ LQ_DEV void apply_slices(typename Tr<P>::acc (&bot)[NS][NB / 16], typename Tr<P>
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int qb = 0; qb < NQ; ++qb) {
+                const f4 y = PRE ? va[qb][rb] : vw(qb, rb);
 #pragma unroll
-                for (int qb = 0; qb < NQ; ++qb)
-#pragma unroll
-                    for (int ns = 0; ns < NS; ++ns)
-                        Wc[ns][rb & 1][qb] = Tr<P>::mma(va[qb][rb][r], bot[ns][rb][r], Wc[ns][rb & 1][qb]);
+                for (int r = 0; r < 4; ++r) Wc[rb & 1][qb] = Tr<P>::mma(y[r], bot[rb][r], Wc[rb & 1][qb]);
+            }
     } else if constexpr (P == P64) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int qb = 0; qb < NQ; ++qb) {
-                    const S y = Yc[(16 * qb + i16) * LDY + 16 * rb + Tr<P>::drow(g, r)];
-#pragma unroll
-                    for (int ns = 0; ns < NS; ++ns) Wc[ns][rb & 1][qb] = Tr<P>::mma(y, bot[ns][rb][r], Wc[ns][rb & 1][qb]);
-                }
+                for (int qb = 0; qb < NQ; ++qb)
+                    Wc[rb & 1][qb] = Tr<P>::mma(Yc[(16 * qb + i16) * LDY + 16 * rb + Tr<P>::drow(g, r)], bot[rb][r],
+                                                Wc[rb & 1][qb]);
     } else {
 #pragma unroll
         for (int pr = 0; pr < NB / 32; ++pr) {
+            bf8 bo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bo[e] = (__bf16)bot[2 * pr + (e >> 2)][e & 3];
 #pragma unroll
             for (int qb = 0; qb < NQ; ++qb) {
-                const f4 lo = *(const f4 *)&Yc[(16 * qb + i16) * LDY + 32 * pr + 4 * g];
-                const f4 hi = *(const f4 *)&Yc[(16 * qb + i16) * LDY + 32 * pr + 16 + 4 * g];
+                const f4 lo = vw(qb, 2 * pr), hi = vw(qb, 2 * pr + 1);
                 bf8 a;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     a[e] = (__bf16)lo[e];
                     a[4 + e] = (__bf16)hi[e];
                 }
-#pragma unroll
-                for (int ns = 0; ns < NS; ++ns) {
-                    bf8 bo;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) bo[e] = (__bf16)bot[ns][2 * pr + (e >> 2)][e & 3];
-                    Wc[ns][pr & 1][qb] = Tr<PB16>::mma(a, bo, Wc[ns][pr & 1][qb]);
-                }
+                Wc[pr & 1][qb] = Tr<PB16>::mma(a, bo, Wc[pr & 1][qb]);
             }
         }
     }
-    acc_t Wb[NS][NQ];
+    acc_t Wb[NQ];
 #pragma unroll
-    for (int ns = 0; ns < NS; ++ns)
+    for (int h = 0; h < NQ; ++h)
 #pragma unroll
-        for (int h = 0; h < NQ; ++h)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                Wb[ns][h][r] = Wc[ns][0][h][r] + Wc[ns][1][h][r];
-                if constexpr (HAS_TOP) Wb[ns][h][r] += tv[ns][h][r];
-            }
+        for (int r = 0; r < 4; ++r) {
+            Wb[h][r] = Wc[0][h][r] + Wc[1][h][r];
+            if constexpr (HAS_TOP) Wb[h][r] += tv[h][r];
+        }
     // W' = T^T W
-    acc_t Wp[NS][NQ];
+    acc_t Wp[NQ];
 #pragma unroll
-    for (int ns = 0; ns < NS; ++ns)
-#pragma unroll
-        for (int ob = 0; ob < NQ; ++ob) Wp[ns][ob] = zero_acc<acc_t>();
+    for (int ob = 0; ob < NQ; ++ob) Wp[ob] = zero_acc<acc_t>();
 #pragma unroll
     for (int qb = 0; qb < NQ; ++qb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int ob = 0; ob < NQ; ++ob) {
-                const S tt = Ts[(16 * ob + i16) * IB + 16 * qb + Tr<P>::drow(g, r)];
-#pragma unroll
-                for (int ns = 0; ns < NS; ++ns) Wp[ns][ob] = Tr<P2>::mma(tt, Wb[ns][qb][r], Wp[ns][ob]);
-            }
+            for (int ob = 0; ob < NQ; ++ob)
+                Wp[ob] = Tr<P2>::mma(Ts[(16 * ob + i16) * IB + 16 * qb + Tr<P>::drow(g, r)], Wb[qb][r], Wp[ob]);
     if constexpr (HAS_TOP) {
 #pragma unroll
-        for (int ns = 0; ns < NS; ++ns)
+        for (int h = 0; h < NQ; ++h)
 #pragma unroll
-            for (int h = 0; h < NQ; ++h)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    top[ns][IB * b + 16 * h + Tr<P>::drow(g, r)] = (S)(tv[ns][h][r] - Wp[ns][h][r]);
+            for (int r = 0; r < 4; ++r) top[IB * b + 16 * h + Tr<P>::drow(g, r)] = (S)(tv[h][r] - Wp[h][r]);
     }
     // bot -= V W', as bot += V (-W'): the sign goes on the NQ x 4 values of W'
     // once rather than on each of the V operands
 #pragma unroll
-    for (int ns = 0; ns < NS; ++ns)
-#pragma unroll
-        for (int ob = 0; ob < NQ; ++ob) Wp[ns][ob] = -Wp[ns][ob];
+    for (int ob = 0; ob < NQ; ++ob) Wp[ob] = -Wp[ob];
     if constexpr (P == P32) {
-        if constexpr (NS > 1) {
-            load_ua();
-            __builtin_amdgcn_sched_barrier(0);
-        }
 #pragma unroll
         for (int ob = 0; ob < NQ; ++ob)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int rb = 0; rb < RB; ++rb) {
+                const f4 y = PRE ? ua[ob][rb] : vu(ob, rb);
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                    for (int ns = 0; ns < NS; ++ns)
-                        bot[ns][rb] = Tr<P>::mma(ua[ob][rb][r], Wp[ns][ob][r], bot[ns][rb]);
+                for (int r = 0; r < 4; ++r) bot[rb] = Tr<P>::mma(y[r], Wp[ob][r], bot[rb]);
+            }
     } else if constexpr (P == P64) {
 #pragma unroll
         for (int ob = 0; ob < NQ; ++ob)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const S y = Yr[(16 * rb + i16) * LDQ + 16 * ob + Tr<P>::drow(g, r)];
-#pragma unroll
-                    for (int ns = 0; ns < NS; ++ns) bot[ns][rb] = Tr<P>::mma(y, Wp[ns][ob][r], bot[ns][rb]);
-                }
+                for (int rb = 0; rb < RB; ++rb)
+                    bot[rb] = Tr<P>::mma(Yr[(16 * rb + i16) * LDQ + 16 * ob + Tr<P>::drow(g, r)], Wp[ob][r], bot[rb]);
     } else {
         // K = 32 per MFMA; a 16-reflector block fills the second half with zeros
-        bf8 bw[NS];
+        bf8 bw;
 #pragma unroll
-        for (int ns = 0; ns < NS; ++ns)
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                bw[ns][e] = (e >> 2) < NQ ? (__bf16)Wp[ns][(e >> 2) % NQ][e & 3] : (__bf16)0.0f;
+        for (int e = 0; e < 8; ++e) bw[e] = (e >> 2) < NQ ? (__bf16)Wp[(e >> 2) % NQ][e & 3] : (__bf16)0.0f;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             bf8 a;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-                if (h < NQ) v = *(const f4 *)&Yr[(16 * rb + i16) * LDQ + 16 * h + 4 * g];
+                if (h < NQ) v = vu(h, rb);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) a[4 * h + e] = (__bf16)v[e];
             }
-#pragma unroll
-            for (int ns = 0; ns < NS; ++ns) bot[ns][rb] = Tr<PB16>::mma(a, bw[ns], bot[ns][rb]);
+            bot[rb] = Tr<PB16>::mma(a, bw, bot[rb]);
         }
     }
-}
-
-// One 16-column slice per wave.
-template <int NB, int P, bool HAS_TOP>
-LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *top, int b,
-                        const typename Tr<P>::S *Ys, const typename Tr<P>::S *Ts) {
-    typedef typename Tr<P>::acc acc_t;
-    typename Tr<P>::S *const tp[1] = {top};
-    apply_slices<NB, P, HAS_TOP, 1>(*reinterpret_cast<acc_t(*)[1][NB / 16]>(&bot), tp, b, Ys, Ts);
 }
 
 // Staging of block reflector b of tile V (column block c0 = b*IB) and its T
@@ -474,7 +428,7 @@ LQ_DEV void stage_block(const S *V, const S *T, int c0, S *Ys, S *Ts) {
 
 // Trailing update of a producer panel: columns (b+1)*IB..NB-1 of A (and, for
 // TS, rows b*IB..b*IB+IB of R) in 64-column strips, with the consumer routine.
-template <int NB, int P, bool TS>
+template <int NB, int P, bool TS, bool PRE = true>
 LQ_DEV void panel_trailing(typename Tr<P>::S *A, typename Tr<P>::S *R, int b, const typename Tr<P>::S *Ys,
                            const typename Tr<P>::S *Ts) {
     typedef typename Tr<P>::S S;
@@ -488,7 +442,7 @@ LQ_DEV void panel_trailing(typename Tr<P>::S *A, typename Tr<P>::S *R, int b, co
         for (int rb = 0; rb < NB / 16; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) bot[rb][r] = A[(16 * rb + Tr<P>::drow(g, r)) + (col + i16) * NB];
-        apply_block<NB, P, TS>(bot, TS ? R + (col + i16) * NB : nullptr, b, Ys, Ts);
+        apply_block<NB, P, TS, PRE>(bot, TS ? R + (col + i16) * NB : nullptr, b, Ys, Ts);
         // GEQRT: rows above the block are untouched by its reflectors and belong
         // to R row blocks other producers are updating: write back rows >= c0 only
 #pragma unroll
@@ -505,10 +459,9 @@ template <int NB, int P> constexpr int qr_lds() {
     return (qr_vblk<NB>() + 2 * IB * IB) * (int)sizeof(typename Tr<P>::S) + (int)sizeof(PanelLds);
 }
 
-// Consumer strips: NS x 64 columns per workgroup (NS 16-column slices per
-// wave), so a tile column holds qr_spc strips; for nb = 32 one strip with two
+// Consumer strips of 64 columns (16 per wave); for nb = 32 one strip with two
 // active waves.
-template <int NB, int NS = 1> constexpr int qr_spc() { return NB >= 64 * NS ? NB / (64 * NS) : 1; }
+template <int NB> constexpr int qr_spc() { return NB >= 64 ? NB / 64 : 1; }
 
 template <int NB> constexpr int qr_pw() { return NB / IB; }  // producer workgroups
 
@@ -516,7 +469,7 @@ LQ_DEV int *qr_flag(const Ctx &c, int i, int b) { return &c.flags[(size_t)i * (c
 
 // Producer workgroup b of one QR step: block b of GEQRT(A_kk), then block b
 // of each TSQRT(A_kk, A_ik) in order of i.
-template <int NB, int P>
+template <int NB, int P, bool PRE>
 LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
     typedef typename Tr<P>::S S;
     constexpr int PP = (P == PB16) ? P32 : P;  // panel-internal updates stay in the storage precision
@@ -542,7 +495,7 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
         if (i == k) {
             panel_qr<NB, S, false>(Akk, c0, nullptr, Ys, Ts, pl);
             for (int e = tid; e < IB * IB; e += WG) Ti[(c0 + e % IB) + (c0 + e / IB) * NB] = Ts[e];
-            panel_trailing<NB, PP, false>(Akk, nullptr, b, Ys, Ts);
+            panel_trailing<NB, PP, false, PRE>(Akk, nullptr, b, Ys, Ts);
         } else {
             S *Aik = At + c.toff(i, k);
             for (int e = tid; e < IB * IB; e += WG) {  // Rb row-major: Rb[p*IB + q] = R(p, q)
@@ -556,7 +509,7 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
                 if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[p * IB + q];
                 Ti[(c0 + p) + (c0 + q) * NB] = Ts[e];
             }
-            panel_trailing<NB, PP, true>(Aik, Akk, b, Ys, Ts);
+            panel_trailing<NB, PP, true, PRE>(Aik, Akk, b, Ys, Ts);
         }
         fence_release();  // every thread's writes of unit (i, b) before the flag
         __syncthreads();
@@ -565,39 +518,33 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
 }
 
 // Consumer LDS: two staging buffers (block s is applied from one while block
-// s+1 is written into the other) and, for 4-byte storage with nb <= 256, the
-// eliminator row strip A_kj (64 columns x nb rows) for the whole chain.
-template <int NB> constexpr int qr_ldt() { return NB + 4; }  // column stride of the LDS strip
+// s+1 is written into the other).  When they and the producer's panel fit in
+// half the LDS (4-byte storage, nb <= 256) the kernel is built for two
+// workgroups per CU: then every workgroup of the widest steps is resident at
+// once, and one workgroup's barriers, flag waits and staging overlap the
+// other's MFMAs.  Otherwise (FP64, nb = 512) one workgroup per CU.
 template <int NB, int P> constexpr int qr_stage_lds() {
     return 2 * (qr_vblk<NB>() + IB * IB) * (int)sizeof(typename Tr<P>::S);
 }
-template <int NB, int P, int NS> constexpr bool qr_top_lds() {
-    return NS == 1 && sizeof(typename Tr<P>::S) == 4 && qr_stage_lds<NB, P>() + 64 * qr_ldt<NB>() * 4 <= 150 * 1024;
+template <int NB, int P> constexpr int qr_step_lds() {
+    return qr_lds<NB, P>() > qr_stage_lds<NB, P>() ? qr_lds<NB, P>() : qr_stage_lds<NB, P>();
 }
-template <int NB, int P, int NS> constexpr int qr_cons_lds() {
-    return qr_stage_lds<NB, P>() + (qr_top_lds<NB, P, NS>() ? 64 * qr_ldt<NB>() * 4 : 0);
-}
-template <int NB, int P, int NS> constexpr int qr_step_lds() {
-    return qr_lds<NB, P>() > qr_cons_lds<NB, P, NS>() ? qr_lds<NB, P>() : qr_cons_lds<NB, P, NS>();
-}
+template <int NB, int P> constexpr int qr_occ() { return qr_step_lds<NB, P>() <= 80 * 1024 ? 2 : 1; }
 
-// NS = 2 (two slices per wave, half the consumer workgroups) is used when one
-// workgroup per strip would not fit on the CUs at once.
-template <int NB, int P, int NS>
-__global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
+template <int NB, int P>
+__global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k) {
     if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
-    constexpr int LDT = qr_ldt<NB>(), VB = qr_vblk<NB>();
+    constexpr int VB = qr_vblk<NB>();
     constexpr int NBLK = NB / IB;
-    constexpr bool TLDS = qr_top_lds<NB, P, NS>();
-    static_assert(NS == 1 || NB >= 64 * NS, "a strip lies within one tile column");
-    __shared__ __attribute__((aligned(16))) char smem[qr_step_lds<NB, P, NS>()];
+    constexpr bool PRE = false;  // bulk operand loads would exceed the registers at nb >= 256
+    __shared__ __attribute__((aligned(16))) char smem[qr_step_lds<NB, P>()];
     if ((int)blockIdx.x < qr_pw<NB>()) {
-        qr_producer<NB, P>(c, k, (int)blockIdx.x, smem);
+        qr_producer<NB, P, PRE>(c, k, (int)blockIdx.x, smem);
         return;
     }
-    // Consumer: one strip of NS x 64 columns of trailing tile column j.  The blocks it
+    // Consumer: one 64-column strip of trailing tile column j.  The blocks it
     // applies form one sequence s = 0 .. (n-k)*NBLK-1: block b of tile i =
     // k + s/NBLK, first the UNMQR blocks of the GEQRT tile (i = k) on A_kj,
     // then the TSMQR blocks of every A_ik on (A_kj, A_ij).  Block s+1 is
@@ -615,43 +562,31 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
     const int epoch = k + 1;
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
     const int strip = (int)blockIdx.x - qr_pw<NB>();
-    const int j = k + 1 + strip / qr_spc<NB, NS>();
-    const int col0 = (strip % qr_spc<NB, NS>()) * 64 * NS + 16 * w;  // slice ns: columns col0 + 64 ns ..
+    const int j = k + 1 + strip / qr_spc<NB>();
+    const int col0 = (strip % qr_spc<NB>()) * 64 + 16 * w;
     const bool active = col0 < NB;
     const int g = l >> 4, i16 = l & 15;
     S *const Y0 = (S *)smem;          // staging buffer u: V at Y0 + u*VB, T at T0 + u*IB*IB
     S *const T0 = Y0 + 2 * VB;
-    float *Tops = (float *)(T0 + 2 * IB * IB);  // TLDS only: column c of the strip at Tops[c*LDT]
     __shared__ int bail[2], inval[2];  // for block x: slot x & 1
     S *Akj = At + c.toff(k, j);
-    S *topc[NS];  // this lane's columns of A_kj for the TSMQR blocks
-#pragma unroll
-    for (int ns = 0; ns < NS; ++ns) {
-        if constexpr (TLDS) topc[ns] = (S *)(Tops + (16 * w + i16) * LDT);
-        else topc[ns] = Akj + (col0 + 64 * ns + i16) * NB;
-    }
+    S *const topc = Akj + (col0 + i16) * NB;  // this lane's column of A_kj for the TSMQR blocks
     const int nblocks = (c.n - k) * NBLK;
     auto vtile = [&](int s) { return At + c.toff(k + s / NBLK, k); };
     auto ttile = [&](int s) { return Tf + c.tqoff(k + s / NBLK, k); };
     auto flag_of = [&](int s) { return qr_flag(c, k + s / NBLK, s % NBLK); };
-    acc_t bot[NS][NB / 16];
+    acc_t bot[NB / 16];
     auto load_bot = [&](const S *src) {
 #pragma unroll
-        for (int ns = 0; ns < NS; ++ns)
+        for (int rb = 0; rb < NB / 16; ++rb)
 #pragma unroll
-            for (int rb = 0; rb < NB / 16; ++rb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    bot[ns][rb][r] = src[(16 * rb + Tr<P>::drow(g, r)) + (col0 + 64 * ns + i16) * NB];
+            for (int r = 0; r < 4; ++r) bot[rb][r] = src[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB];
     };
     auto store_bot = [&](S *dst) {
 #pragma unroll
-        for (int ns = 0; ns < NS; ++ns)
+        for (int rb = 0; rb < NB / 16; ++rb)
 #pragma unroll
-            for (int rb = 0; rb < NB / 16; ++rb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    dst[(16 * rb + Tr<P>::drow(g, r)) + (col0 + 64 * ns + i16) * NB] = (S)bot[ns][rb][r];
+            for (int r = 0; r < 4; ++r) dst[(16 * rb + Tr<P>::drow(g, r)) + (col0 + i16) * NB] = (S)bot[rb][r];
     };
     auto tile_end = [&](int s) { return (s / NBLK) * NBLK + NBLK - 1; };
     int covered = 1;  // thread 0: blocks 0..covered are acquired
@@ -686,21 +621,10 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
                                          __HIP_MEMORY_SCOPE_AGENT);
         if (active) {
             const S *Yc = Y0 + cur * VB, *Tc = T0 + cur * (IB * IB);
-            if (i == k) apply_slices<NB, P, false, NS>(bot, topc, b, Yc, Tc);
-            else apply_slices<NB, P, true, NS>(bot, topc, b, Yc, Tc);
-            if (b == NBLK - 1) {  // tile i done: hand A_kj to the LDS strip, or write A_ij back
-                if (i == k) {
-                    if constexpr (TLDS) {
-#pragma unroll
-                        for (int rb = 0; rb < NB / 16; ++rb)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) topc[0][16 * rb + Tr<P>::drow(g, r)] = (S)bot[0][rb][r];
-                    } else {
-                        store_bot(Akj);
-                    }
-                } else {
-                    store_bot(At + c.toff(i, j));
-                }
+            if (i == k) apply_block<NB, P, false, PRE>(bot, nullptr, b, Yc, Tc);
+            else apply_block<NB, P, true, PRE>(bot, topc, b, Yc, Tc);
+            if (b == NBLK - 1) {  // tile i done: write it back, start on the next
+                store_bot(i == k ? Akj : At + c.toff(i, j));
                 if (i + 1 < c.n) load_bot(At + c.toff(i + 1, j));
             }
         }
@@ -724,17 +648,6 @@ __global__ __launch_bounds__(WG, 1) void k_qr_step(Ctx c, int k) {
             inval[s & 1] = inv;
         }
         __syncthreads();
-    }
-    if constexpr (TLDS) {  // the finished rows of A_kj
-        if (active) {
-#pragma unroll
-            for (int rb = 0; rb < NB / 16; ++rb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * rb + Tr<P>::drow(g, r);
-                    Akj[row + (col0 + i16) * NB] = topc[0][row];
-                }
-        }
     }
 }
 

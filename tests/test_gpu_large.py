@@ -1,14 +1,14 @@
-"""QR steps whose trailing matrix is wide enough that one consumer workgroup
-per 64-column strip would not fit on the device at once: there the QR-step
-kernel gives each wave two 16-column slices (half as many workgroups).  At
-N = 16384, n_b = 256 this holds for the first steps (16 producers +
-4 (n-k-1) strips > 256 CUs); alpha = 0 makes every step a QR step (Sec. 3).
+"""QR steps whose trailing matrix is wide enough that the QR-step grid (16
+producers + 4 (n-k-1) consumer strips at n_b = 256) exceeds the CU count, so
+that the kernel relies on two workgroups being resident per CU.  At
+N = 16384, n_b = 256 this holds for the first steps; alpha = 0 makes every
+step a QR step (Sec. 3).
 
 The oracle does not reach this size, so the bar is the solution-level one of
 the mixed-precision tests: refinement reaches backward error <= N 1e-16 in a
 few passes (it would not with a wrong trailing update), and the refined
-solution agrees with the FP64 GPU path, which uses one slice per wave
-throughout, within 4 cond N 1e-16 (cond bounded by N kappa for UΣV^T).
+solution agrees with the FP64 GPU path (one workgroup per CU) within
+4 cond N 1e-16 (cond bounded by N kappa for UΣV^T).
 """
 import numpy as np
 import pytest
@@ -46,7 +46,7 @@ def x64(system):
 
 
 @pytest.mark.parametrize("prec,max_passes", [("fp32", 4), ("bf16", 40)])
-def test_two_slice_qr_steps(system, x64, prec, max_passes):
+def test_wide_qr_steps(system, x64, prec, max_passes):
     from paper_1401_5522_amd import solver
     A, b = system
     f = solver.factor(A, NB, criterion="max", alpha=0.0, precision=prec)
