@@ -100,10 +100,102 @@ __global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
 // product accumulates in FP32 and is scaled back exactly.
 template <int NB> constexpr int upd_bt() { return NB >= 128 ? 128 : NB; }
 
+// FP32 storage, nb >= 128: a dedicated 128 x 128 x nb tile product.
+//   * K runs in chunks of 32, staged in LDS K-contiguous: As[m][k] (A_ik is
+//     column-major, so each thread transposes a 4 x 4 block in registers)
+//     and Bs[n][k] (A_kj columns are K-contiguous already), row stride 36.
+//   * Lane (i16, g) takes K index 16 G + 4 g + s in step s of group G, for A
+//     and B alike, so each MFMA operand comes from one 128-bit LDS read that
+//     serves four MFMAs; with stride 36 the sixteen lanes of a quarter-wave
+//     hit sixteen disjoint bank groups.
+//   * The next chunk is loaded into registers while the current one is
+//     multiplied, then stored into the other LDS buffer: one barrier a chunk.
+//   * Four waves of 64 x 64 (4 x 4 MFMA blocks of 16 x 16); the update of C
+//     reads and writes four consecutive rows per lane (16 bytes).
+// 74 KB of LDS and at most 256 registers: two workgroups per CU.
+constexpr int UPD_BK = 32, UPD_LD = UPD_BK + 4;
+constexpr int upd_lds_floats() { return 2 * 2 * 128 * UPD_LD; }
+
+template <int NB>
+LQ_DEV void lu_update_f32(const float *__restrict__ Aik, const float *__restrict__ Akj, float *__restrict__ C,
+                          int r0, int c0, float *sm) {
+    const int tid = threadIdx.x, l = lane_id(), w = wave_id(), g = l >> 4, i16 = l & 15;
+    const int m0 = (w & 1) * 64, n0 = (w >> 1) * 64;  // the wave's 64 x 64 block
+    // staging assignment: A: 4 rows (4 m4 ..) x 4 k (4 kq ..); B: row n = tid / 2, 16 k from 16 (tid & 1)
+    const int m4 = tid & 31, kq = tid >> 5, bn = tid >> 1, bh = tid & 1;
+    f4 ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ra[u] = *(const f4 *)&Aik[(r0 + 4 * m4) + (size_t)(k0 + 4 * kq + u) * NB];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rb[u] = *(const f4 *)&Akj[(k0 + 16 * bh + 4 * u) + (size_t)(c0 + bn) * NB];
+    };
+    auto store = [&](int buf) {
+        float *As = sm + buf * (2 * 128 * UPD_LD), *Bs = As + 128 * UPD_LD;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)  // row 4 m4 + i of the 4 x 4 block, k = 4 kq .. 4 kq + 3
+            *(f4 *)&As[(4 * m4 + i) * UPD_LD + 4 * kq] = (f4){ra[0][i], ra[1][i], ra[2][i], ra[3][i]};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) *(f4 *)&Bs[bn * UPD_LD + 16 * bh + 4 * u] = rb[u];
+    };
+    f4 acc[4][4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+    load(0);
+    store(0);
+    __syncthreads();
+    constexpr int NCH = NB / UPD_BK;
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < NCH) load((ch + 1) * UPD_BK);
+        const float *As = sm + buf * (2 * 128 * UPD_LD), *Bs = As + 128 * UPD_LD;
+#pragma unroll
+        for (int G = 0; G < UPD_BK / 16; ++G) {
+            f4 a[4], bv[4];
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) a[mb] = *(const f4 *)&As[(m0 + 16 * mb + i16) * UPD_LD + 16 * G + 4 * g];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) bv[nb] = *(const f4 *)&Bs[(n0 + 16 * nb + i16) * UPD_LD + 16 * G + 4 * g];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][s], bv[nb][s], acc[mb][nb], 0, 0, 0);
+        }
+        if (ch + 1 < NCH) store(buf ^ 1);
+        __syncthreads();
+    }
+    // C -= acc: lane (i16, g) owns rows 16 mb + 4 g .. + 3 of column 16 nb + i16
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            f4 *p = (f4 *)&C[(r0 + m0 + 16 * mb + 4 * g) + (size_t)(c0 + n0 + 16 * nb + i16) * NB];
+            *p = *p - acc[mb][nb];
+        }
+}
+
+template <int P> constexpr int upd_occ() { return P == P32 ? 2 : 1; }
+
 template <int NB, int P>
-__global__ __launch_bounds__(WG) void k_lu_update(Ctx c, int k) {
+__global__ __launch_bounds__(WG, (upd_occ<P>())) void k_lu_update(Ctx c, int k) {
     if (c.dec[k] != 1) return;
     typedef typename Tr<P>::S S;
+    if constexpr (P == P32 && NB >= 128) {
+        __shared__ __attribute__((aligned(16))) float sm[upd_lds_floats()];
+        constexpr int PER = NB / 128;
+        const int rest = (int)c.n - k - 1;
+        const int b = blockIdx.x, sub = b % (PER * PER), t = b / (PER * PER);
+        const int i = k + 1 + t % rest, j = k + 1 + t / rest;
+        const float *At = (const float *)c.At;
+        lu_update_f32<NB>(At + c.toff(i, k), At + c.toff(k, j), (float *)c.At + c.toff(i, j), (sub % PER) * 128,
+                          (sub / PER) * 128, sm);
+        return;
+    } else {
     constexpr int BT = upd_bt<NB>();
     constexpr int BK = (P == PB16) ? 32 : 16;
     constexpr int PER = NB / BT;
@@ -129,6 +221,7 @@ __global__ __launch_bounds__(WG) void k_lu_update(Ctx c, int k) {
         S *p = Cij + (r0 + r) + (size_t)(c0 + cc) * NB;
         *p = (S)((double)*p - v * inv);
     });
+    }
 }
 
 }  // namespace lq
