@@ -699,13 +699,21 @@ __global__ __launch_bounds__(WG) void k_qr_gram(Ctx c, int k) {
 
 // Off-diagonal blocks of T, block column by block column; one workgroup per
 // panel tile, grid n-k.  FP64 arithmetic, storage precision result.
+// For block column b (c0 = b IB): Y1 = T(0:c0, 0:c0) G(0:c0, c0:c0+IB), then
+// T(0:c0, c0:c0+IB) = -Y1 T_b.  Y1 runs over 16-column chunks of T, each
+// staged in LDS with coalesced loads (the strictly lower part, which the
+// workspace does not hold, is masked to zero on staging); thread (a1, q)
+// accumulates rows a1 + AS m of column q.
 template <int NB, int P>
 __global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k) {
     if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
-    constexpr int AS = WG / IB;        // row stride: thread tid takes rows tid/IB + AS m
+    constexpr int AS = WG / IB;         // row stride: thread tid takes rows tid/IB + AS m
     constexpr int MR = (NB - IB) / AS;  // rows a per thread at most
-    __shared__ double Gs[(NB - IB) * IB];  // G(0:c, c:c+IB), then Y1 = T(0:c,0:c) G(...)
+    constexpr int CH = 16;              // columns of T per staged chunk
+    __shared__ double Tc[CH * (NB - IB)];  // chunk of T(0:c0, a2c..a2c+CH), [col][row]
+    __shared__ double Gc[CH * IB];         // G(a2c..a2c+CH, c0..c0+IB), [row][q]
+    __shared__ double Y1[(NB - IB) * IB];  // Y1[a*IB + p]
     __shared__ double Tb[IB * IB];
     const int t = blockIdx.x, i = k + t;
     S *T = (S *)c.Tf + c.tqoff(i, k);
@@ -713,34 +721,48 @@ __global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k) {
     const int tid = threadIdx.x, q = tid & (IB - 1), a1 = tid / IB;
     for (int b = 1; b < NB / IB; ++b) {
         const int c0 = b * IB;
-        for (int e = tid; e < c0 * IB; e += WG) Gs[e] = G[(e / IB) + (size_t)(c0 + e % IB) * NB];  // Gs[a*IB + q]
         for (int e = tid; e < IB * IB; e += WG) {
             const int pp = e / IB, qq = e % IB;
             Tb[e] = pp <= qq ? (double)T[(c0 + pp) + (size_t)(c0 + qq) * NB] : 0.0;  // Tb[p*IB + q]
         }
-        __syncthreads();
-        double y1[MR];
+        double acc[MR];
 #pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int a = a1 + AS * m;
-            double acc = 0.0;
-            if (a < c0)
-                for (int a2 = a; a2 < c0; ++a2) acc += (double)T[a + (size_t)a2 * NB] * Gs[a2 * IB + q];
-            y1[m] = acc;
+        for (int m = 0; m < MR; ++m) acc[m] = 0.0;
+        for (int a2c = 0; a2c < c0; a2c += CH) {
+            const int rows = a2c + CH;  // rows 0..a2c+CH-1 can be nonzero in these columns
+            __syncthreads();             // previous chunk consumed
+            for (int e = tid; e < CH * rows; e += WG) {
+                const int r = e % rows, cc = e / rows, a2 = a2c + cc;
+                Tc[cc * (NB - IB) + r] = r <= a2 ? (double)T[r + (size_t)a2 * NB] : 0.0;
+            }
+            for (int e = tid; e < CH * IB; e += WG) {
+                const int rr = e / IB, qq = e % IB;
+                Gc[e] = G[(a2c + rr) + (size_t)(c0 + qq) * NB];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < MR; ++m) {
+                const int a = a1 + AS * m;
+                if (a < rows) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int cc = 0; cc < CH; ++cc) s += Tc[cc * (NB - IB) + a] * Gc[cc * IB + q];
+                    acc[m] += s;
+                }
+            }
         }
-        __syncthreads();
 #pragma unroll
         for (int m = 0; m < MR; ++m) {
             const int a = a1 + AS * m;
-            if (a < c0) Gs[a * IB + q] = y1[m];
+            if (a < c0) Y1[a * IB + q] = acc[m];
         }
         __syncthreads();
         for (int a = a1; a < c0; a += AS) {
-            double acc = 0.0;
-            for (int pp = 0; pp <= q; ++pp) acc += Gs[a * IB + pp] * Tb[pp * IB + q];
-            T[a + (size_t)(c0 + q) * NB] = (S)(-acc);
+            double s = 0.0;
+            for (int pp = 0; pp <= q; ++pp) s += Y1[a * IB + pp] * Tb[pp * IB + q];
+            T[a + (size_t)(c0 + q) * NB] = (S)(-s);
         }
-        __syncthreads();
+        __syncthreads();  // this block column is written before the next reads it
     }
 }
 
