@@ -20,7 +20,8 @@
  *    the luqr_get_* calls, which wait for the stream.
  *  - The library never allocates device memory: the caller provides one
  *    workspace whose size luqr_workspace_bytes reports and keeps it alive
- *    until luqr_destroy.  The library owns only the small host handle.
+ *    until luqr_destroy.  The library owns only the small host handle and,
+ *    for the lookahead of luqr_factor, one stream and two events of its own.
  *  - Return codes: 0 = success; -i = argument i (1-based) is invalid;
  *    LUQR_ERR_UNSUPPORTED for a valid but unimplemented combination;
  *    LUQR_ERR_HIP - e for a HIP runtime error e.  Numerical conditions
@@ -73,7 +74,12 @@ typedef struct {
     int32_t mumps_reading; /* 0 (default): estimate_max(j) = away_max(j) * prod_{i<j} growth(i) */
     int32_t timing;      /* nonzero: record HIP events between the kernels of each step
                             (read back with luqr_get_step_times) */
-    int32_t reserved;
+    int32_t no_lookahead;/* 0 (default): lookahead (the Sec. 4 task graph's overlap of
+                            consecutive steps): step k+1's panel factor and criterion run
+                            while step k's bulk trailing work (LU: columns k+2.., QR: R^-1
+                            and the full T factors) runs on a second stream of the
+                            library's own, joined before step k+1's branch; nonzero: every
+                            kernel in order on the caller's stream */
 } luqr_opts;
 
 /* Device-side numerical status, read back by luqr_get_status. */
@@ -99,9 +105,11 @@ int64_t luqr_workspace_bytes(int64_t N, const luqr_opts *opts);
  * FP64, not modified) with the hybrid LU-QR algorithm (Alg. 1).  Factors,
  * decisions and all scratch live in dWork (device, >= luqr_workspace_bytes,
  * 256-byte aligned).  On success *out receives a new handle.  Asynchronous:
- * returns once the work is enqueued on `stream`.  The decision of step k is
- * written on the device and read there by the LU and QR branch kernels: the
- * host never waits for it. */
+ * returns once the work is enqueued on `stream` (with lookahead, part of it on
+ * the handle's own stream, which is joined back to `stream` at the end, so work
+ * enqueued on `stream` afterwards sees the whole factorization).  The decision
+ * of step k is written on the device and read there by the LU and QR branch
+ * kernels: the host never waits for it. */
 int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_opts *opts,
                 void *dWork, int64_t work_bytes, void *stream, luqr_factors *out);
 

@@ -19,6 +19,7 @@ struct luqr_factors_s {
     int nsteps;
     std::vector<hipEvent_t> ev;  // LUQR_NPHASE + 1 per step when opts.timing is set
     std::vector<int> hdec;       // decision sequence, read once by the first solve
+    Side side{nullptr, nullptr, nullptr};  // lookahead stream and events (unless opts.no_lookahead)
 };
 
 static int hip_rc(hipError_t e) { return e == hipSuccess ? 0 : LUQR_ERR_HIP - (int)e; }
@@ -101,8 +102,15 @@ extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_
             if (he != hipSuccess) { e = nullptr; luqr_destroy(f); return hip_rc(he); }
         }
     }
+    if (!o->no_lookahead) {
+        hipError_t he = hipStreamCreateWithFlags(&f->side.st, hipStreamNonBlocking);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&f->side.ea, hipEventDisableTiming);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&f->side.eb, hipEventDisableTiming);
+        if (he != hipSuccess) { luqr_destroy(f); return hip_rc(he); }
+    }
     (void)hipGetLastError();
-    f->ops->factor(f->c, L, dA, lda, *o, f->nsteps, f->stream, f->ev.empty() ? nullptr : f->ev.data());
+    f->ops->factor(f->c, L, dA, lda, *o, f->nsteps, f->stream, f->ev.empty() ? nullptr : f->ev.data(),
+                   f->side.st ? &f->side : nullptr);
     rc = hip_rc(hipGetLastError());
     if (rc) { luqr_destroy(f); return rc; }
     *out = f;
@@ -291,6 +299,12 @@ extern "C" void luqr_destroy(luqr_factors f) {
     if (!f) return;
     for (auto &e : f->ev)
         if (e) (void)hipEventDestroy(e);
+    if (f->side.st) {
+        (void)hipStreamSynchronize(f->side.st);  // its work was joined to the caller's stream
+        (void)hipStreamDestroy(f->side.st);
+    }
+    if (f->side.ea) (void)hipEventDestroy(f->side.ea);
+    if (f->side.eb) (void)hipEventDestroy(f->side.eb);
     delete f;
 }
 

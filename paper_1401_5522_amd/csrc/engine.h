@@ -1,5 +1,5 @@
 // Host-side launch sequences.  The host enqueues every kernel of every step
-// on one stream without waiting: the LU-or-QR decision of step k is written
+// without waiting (on one stream, or two with lookahead): the LU-or-QR decision of step k is written
 // to device memory by k_panel_decide and both branch kernels read it there,
 // returning at once when they are not the chosen branch (the dynamic task
 // graph of Sec. 4 without a host round trip).
@@ -11,9 +11,16 @@
 
 namespace lq {
 
+// Lookahead resources owned by a factorization handle: a second stream (default
+// priority) and two events that order it against the caller's stream.
+struct Side {
+    hipStream_t st;
+    hipEvent_t ea, eb;
+};
+
 struct Ops {
     void (*factor)(const Ctx &, const Layout &, const double *A, int64_t lda, const luqr_opts &, int nsteps,
-                   hipStream_t, hipEvent_t *ev);
+                   hipStream_t, hipEvent_t *ev, const Side *side);
     void (*solve)(const Ctx &, const Layout &, SolveArgs, const int *hdec, hipStream_t);
     void (*export_factors)(const Ctx &, const Layout &, double *F, int64_t ldf, hipStream_t);
 };
@@ -26,8 +33,16 @@ struct Eng {
 
     // ev (optional): LUQR_NPHASE + 1 events per step, one before each phase of
     // luqr_get_step_times and one after the last.
+    // side (optional): lookahead.  Step k's bulk trailing work -- the LU update
+    // of columns k+2.. or the QR step's R^-1, Gram and full T -- goes to
+    // side->st once step k's critical part (LU: Eliminate/Apply and the update
+    // of column k+1; QR: the QR step) is done (event ea), so that step k+1's
+    // panel factor, norms and decision run meanwhile on st; step k+1's branch
+    // kernels wait for it (event eb).  The panel of step k+1 reads only tile
+    // column k+1, which the critical part has finished, and writes only its
+    // own per-step buffers.
     static void factor(const Ctx &c, const Layout &L, const double *A, int64_t lda, const luqr_opts &o, int nsteps,
-                       hipStream_t st, hipEvent_t *ev) {
+                       hipStream_t st, hipEvent_t *ev, const Side *side) {
         const int n = (int)c.n;
         k_status_reset<<<1, 64, 0, st>>>(c.st);
         k_fill_int<<<nblk((int64_t)n * (NB / IB)), WG, 0, st>>>(c.flags, (int64_t)n * (NB / IB), 0);
@@ -50,22 +65,33 @@ struct Eng {
             a.mumps_reading = o.mumps_reading;
             k_panel_decide<NB><<<1, WG, 0, st>>>(c, k, a);
             if (ev) (void)hipEventRecord(ev[E * k + 1], st);
+            if (side && k > 0) (void)hipStreamWaitEvent(st, side->eb, 0);  // step k-1's bulk work
             k_lu_apply<NB, P><<<1 + 2 * rest * (NB / lu_rb<NB>()), WG, 0, st>>>(c, k);
             if (ev) (void)hipEventRecord(ev[E * k + 2], st);
-            if (rest > 0) {
-                constexpr int PER = NB / upd_bt<NB>();
-                k_lu_update<NB, P><<<(unsigned)rest * rest * PER * PER, WG, 0, st>>>(c, k);
+            constexpr int PER = NB / upd_bt<NB>();
+            if (rest > 0) {  // with lookahead column k+1 only, the rest below
+                const unsigned cols = side ? 1u : (unsigned)rest;
+                k_lu_update<NB, P><<<(unsigned)rest * cols * PER * PER, WG, 0, st>>>(c, k, k + 1);
             }
             if (ev) (void)hipEventRecord(ev[E * k + 3], st);
             k_qr_step<NB, P><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
             if (ev) (void)hipEventRecord(ev[E * k + 4], st);
-            k_qr_rinv<NB, S><<<NB / 4, WG, 0, st>>>(c, k);
-            if constexpr (NB > IB) {
-                k_qr_gram<NB, P><<<dim3(qr_npairs<NB>(), n - k), WG, 0, st>>>(c, k);
-                k_qr_tfull<NB, P><<<n - k, WG, 0, st>>>(c, k);
+            hipStream_t sb = st;
+            if (side) {
+                (void)hipEventRecord(side->ea, st);
+                (void)hipStreamWaitEvent(side->st, side->ea, 0);
+                sb = side->st;
+                if (rest > 1) k_lu_update<NB, P><<<(unsigned)rest * (rest - 1) * PER * PER, WG, 0, sb>>>(c, k, k + 2);
             }
-            if (ev) (void)hipEventRecord(ev[E * k + 5], st);
+            k_qr_rinv<NB, S><<<NB / 4, WG, 0, sb>>>(c, k);
+            if constexpr (NB > IB) {
+                k_qr_gram<NB, P><<<dim3(qr_npairs<NB>(), n - k), WG, 0, sb>>>(c, k);
+                k_qr_tfull<NB, P><<<n - k, WG, 0, sb>>>(c, k);
+            }
+            if (side) (void)hipEventRecord(side->eb, sb);
+            if (ev) (void)hipEventRecord(ev[E * k + 5], sb);
         }
+        if (side) (void)hipStreamWaitEvent(st, side->eb, 0);  // join: the factorization ends on st
     }
 
     // hdec: the decision sequence on the host; only the chosen branch of each

@@ -181,8 +181,11 @@ LQ_DEV void lu_update_f32(const float *__restrict__ Aik, const float *__restrict
 
 template <int P> constexpr int upd_occ() { return P == P32 ? 2 : 1; }
 
+// Tile columns j = jlo .. n-1 (grid: (n-k-1) (n-jlo) tiles x PER^2 blocks):
+// jlo = k+1 for the whole update, or the lookahead column k+1 and the rest
+// k+2.. as two launches.
 template <int NB, int P>
-__global__ __launch_bounds__(WG, (upd_occ<P>())) void k_lu_update(Ctx c, int k) {
+__global__ __launch_bounds__(WG, (upd_occ<P>())) void k_lu_update(Ctx c, int k, int jlo) {
     if (c.dec[k] != 1) return;
     typedef typename Tr<P>::S S;
     if constexpr (P == P32 && NB >= 128) {
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(WG, (upd_occ<P>())) void k_lu_update(Ctx c, int k) 
         constexpr int PER = NB / 128;
         const int rest = (int)c.n - k - 1;
         const int b = blockIdx.x, sub = b % (PER * PER), t = b / (PER * PER);
-        const int i = k + 1 + t % rest, j = k + 1 + t / rest;
+        const int i = k + 1 + t % rest, j = jlo + t / rest;
         const float *At = (const float *)c.At;
         lu_update_f32<NB>(At + c.toff(i, k), At + c.toff(k, j), (float *)c.At + c.toff(i, j), (sub % PER) * 128,
                           (sub / PER) * 128, sm);
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(WG, (upd_occ<P>())) void k_lu_update(Ctx c, int k) 
     int b = blockIdx.x;
     const int sub = b % (PER * PER);
     const int t = b / (PER * PER);
-    const int i = k + 1 + t % rest, j = k + 1 + t / rest;
+    const int i = k + 1 + t % rest, j = jlo + t / rest;
     const int r0 = (sub % PER) * BT, c0 = (sub / PER) * BT;
     S *At = (S *)c.At;
     const S *Aik = At + c.toff(i, k);

@@ -141,3 +141,22 @@ def test_step_times(gpu):
     lu = t[:, gpu.Factors.PHASES.index("lu_update")]
     assert qr[dec == 0].sum() > qr[dec == 1].sum()
     assert lu[:-1][dec[:-1] == 0].max() < qr[:-1][dec[:-1] == 0].min()
+
+
+@pytest.mark.parametrize("prec,alpha", [("fp32", 3e4), ("fp64", 3e4), ("fp32", 0.0)])
+def test_lookahead_is_a_pure_reordering(gpu, prec, alpha):
+    """Lookahead (step k+1's panel during step k's bulk trailing work, on a
+    second stream) only reorders independent kernels: the factors, pivots and
+    decisions must equal those of the strictly ordered run bit for bit."""
+    import torch
+    N, nb = 2048, 256
+    A = torch.from_numpy(inputs.usv(N, 1e2, seed=(116, N))).cuda()
+    runs = []
+    for la in (False, True):
+        f = gpu.factor(A, nb, criterion="max", alpha=alpha, precision=prec, lookahead=la)
+        F, ipiv = f.export()
+        runs.append((F.cpu().numpy(), ipiv, f.decisions()[0]))
+        assert f.status().watchdog == 0
+    (F0, p0, d0), (F1, p1, d1) = runs
+    assert (d0 == d1).all() and (p0 == p1).all()
+    assert np.array_equal(F0, F1)
