@@ -344,8 +344,11 @@ def main():
     torch.cuda.synchronize()
     kw = dict(criterion=args.criterion, alpha=args.alpha, seed=args.seed, nrhs_max=args.nrhs)
 
+    nb64 = min(nb, 256)  # the FP64 path stops at n_b = 256
+
     def run(precision, timing, work):
-        f = solver.factor(A, nb, precision=precision, timing=timing, work=work, **kw)
+        f = solver.factor(A, nb if precision != "fp64" else nb64, precision=precision, timing=timing, work=work,
+                          **kw)
         if precision == "fp64":
             X = f.solve(B)
         else:
@@ -397,11 +400,11 @@ def main():
         t1 = time.perf_counter()
         ms64 = (t1 - t0) * 1e3 / K64
         eta64 = backward_error(A, hs[-1][1], B)
-        fp64 = {"ms_per_step": round(ms64, 3),
+        fp64 = {"nb": nb64, "ms_per_step": round(ms64, 3),
                 "tflops": round(2.0 * N ** 3 / 3.0 / (ms64 * 1e-3) / 1e12, 3),
                 "eta": eta64,
-                "decisions_equal_to_mixed": bool((dec64 == dec).all()),
-                "decisions_differing": int((dec64 != dec).sum()),
+                "decisions_equal_to_mixed": bool(nb64 == nb and (dec64 == dec).all()),
+                "decisions_differing": int((dec64 != dec).sum()) if nb64 == nb else None,
                 "speedup_mixed_over_fp64": round(ms64 / ms, 3)}
         del hs, work
         torch.cuda.empty_cache()

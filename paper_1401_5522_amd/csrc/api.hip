@@ -176,7 +176,7 @@ extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda,
     const int64_t total = L.Np * nrhs;
     (void)hipGetLastError();
     k_ir_reset<<<1, 64, 0, st>>>(f->c.st, conv);
-    k_fill_f64<<<1, 64, 0, st>>>(norms, 2 * nrhs + 1);
+    k_fill_f64<<<nblk(2 * nrhs + 1), WG, 0, st>>>(norms, 2 * nrhs + 1);  // ||r||, ||x|| per column, ||A||
     // x0 = solve(b): solve writes its result into X; keep the iterate in Xk
     SolveArgs s = solve_args(f, nq, nullptr);
     k_rhs_in<<<nblk(total), WG, 0, st>>>(dB, ldb, s.Y, L.N, L.Np, nq, nullptr);
