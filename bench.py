@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16", "fp64"))
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--max-iter", type=int, default=10)
+    ap.add_argument("--refine", default="ir", choices=("ir", "gmres"),
+                    help="refinement of the mixed-precision solve: plain (ir) or GMRES-based (one RHS)")
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 runs (default: --steps; 0 = skip)")
     ap.add_argument("--cpu-N", type=int, default=8192, help="matrix size of the oracle sample (0 = skip)")
@@ -351,6 +353,8 @@ def main():
                           **kw)
         if precision == "fp64":
             X = f.solve(B)
+        elif args.refine == "gmres":
+            X = f.solve_gmres_ir(A, B[:, 0], max_outer=args.max_iter, max_inner=30)[0].reshape(-1, 1)
         else:
             X = f.solve_refined(A, B, max_iter=args.max_iter)
         return f, X
@@ -429,8 +433,9 @@ def main():
         "dtype": DTYPE[prec],
         "data": "synthetic",
         "config": {"workload": f"usv kappa={args.kappa:g} N={N} nb={nb} {args.criterion} alpha={args.alpha:g} "
-                               f"{prec}+fp64-IR nrhs={args.nrhs}",
+                               f"{prec}+fp64-{'GMRES-IR' if args.refine == 'gmres' else 'IR'} nrhs={args.nrhs}",
                    "N": N, "nb": nb, "nrhs": args.nrhs, "kappa": args.kappa, "criterion": args.criterion,
+                   "refine": args.refine,
                    "alpha": args.alpha, "precision": prec, "parallelism": "single GPU"},
         "solves_per_s": round(1e3 / ms, 4),
         "eta": eta,

@@ -136,6 +136,21 @@ int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda, int64_t nr
                        const double *dB, int64_t ldb, double *dX, int64_t ldx,
                        int32_t max_iter, void *stream);
 
+/* GMRES-based iterative refinement for one right-hand side (for factors too
+ * inaccurate for luqr_solve_refined to converge: ill-conditioned A, BF16
+ * contractions).  x0 = solve(b); then up to max_outer times r = b - A x in
+ * FP64 with the same convergence test as luqr_solve_refined, and x += d
+ * where d solves A d = r by GMRES in FP64 left-preconditioned by the stored
+ * factors (each inner step: one product with dA and one solve), restarted
+ * after max_inner (1..30) vectors or once the preconditioned residual has
+ * dropped by 1e-6.  db and dx are device vectors of N doubles.  The host
+ * waits on `stream` once per inner step for two short vectors.  The outer
+ * iteration count and backward error are reported by luqr_get_status; the
+ * number of inner steps is written to *inner_total (host, may be NULL). */
+int luqr_solve_gmres_ir(luqr_factors f, const double *dA, int64_t lda, const double *db,
+                        double *dx, int32_t max_outer, int32_t max_inner,
+                        int32_t *inner_total, void *stream);
+
 /* Copy the decision sequence (1 = LU, 0 = QR), s_k = 1/||A_kk^-1||_1, m_k (the
  * max or sum of sub-diagonal tile norms) and the relative margin
  * (alpha s_k - m_k)/max(alpha s_k, m_k) of the first n steps to host arrays

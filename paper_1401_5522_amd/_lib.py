@@ -16,7 +16,7 @@ LUQR_ERR_HIP = -1000
 CRITERIA = {"max": 0, "sum": 1, "mumps": 2, "random": 3, "forced": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 
-EXPORTED = ["luqr_workspace_bytes", "luqr_factor", "luqr_solve", "luqr_solve_refined",
+EXPORTED = ["luqr_workspace_bytes", "luqr_factor", "luqr_solve", "luqr_solve_refined", "luqr_solve_gmres_ir",
             "luqr_get_decisions", "luqr_get_status", "luqr_get_step_times", "luqr_export_factors", "luqr_destroy",
             "luqr_batched_workspace_bytes", "luqr_batched_plan", "luqr_batched_run", "luqr_batched_decision_stride",
             "luqr_batched_destroy", "luqr_batched_autotune"]
@@ -70,6 +70,8 @@ def lib() -> C.CDLL:
     L.luqr_solve.argtypes = [vp, i64, vp, i64, vp]
     L.luqr_solve_refined.restype = C.c_int
     L.luqr_solve_refined.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, i32, vp]
+    L.luqr_solve_gmres_ir.restype = C.c_int
+    L.luqr_solve_gmres_ir.argtypes = [vp, vp, i64, vp, vp, i32, i32, C.POINTER(C.c_int32), vp]
     L.luqr_get_decisions.restype = C.c_int
     L.luqr_get_decisions.argtypes = [vp, vp, vp, vp, vp, i64]
     L.luqr_get_status.restype = C.c_int
@@ -135,6 +137,13 @@ def luqr_solve(h, nrhs, dB, ldb, stream):
 def luqr_solve_refined(h, dA, lda, nrhs, dB, ldb, dX, ldx, max_iter, stream):
     return check(lib().luqr_solve_refined(h, dA, lda, nrhs, dB, ldb, dX, ldx, max_iter, stream),
                  "luqr_solve_refined")
+
+
+def luqr_solve_gmres_ir(h, dA, lda, db, dx, max_outer, max_inner, stream):
+    inner = C.c_int32(0)
+    check(lib().luqr_solve_gmres_ir(h, dA, lda, db, dx, max_outer, max_inner, C.byref(inner), stream),
+          "luqr_solve_gmres_ir")
+    return inner.value
 
 
 def luqr_get_decisions(h, dec, s, m, margin, n):

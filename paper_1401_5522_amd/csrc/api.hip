@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "krylov.h"
 
 using namespace lq;
 
@@ -205,6 +206,147 @@ extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda,
         k_ir_update<<<nblk(total), WG, 0, st>>>(Xk, D, total, conv);
     }
     k_rhs_out<<<nblk(L.N * nrhs), WG, 0, st>>>(Xk, dX, ldx, L.N, L.Np, nq);
+    return hip_rc(hipGetLastError());
+}
+
+// GMRES-based iterative refinement (one right-hand side).  Outer loop in
+// FP64: r = b - A x, the convergence test of luqr_solve_refined, and x += d
+// where d solves A d = r by GMRES(m) in FP64, left-preconditioned by the
+// stored factors (M^{-1} = the hybrid LU-QR solve): the Arnoldi basis is
+// orthogonalized by classical Gram-Schmidt applied twice, the small
+// Hessenberg least-squares problem is solved on the host with Givens
+// rotations, and the inner loop stops when the preconditioned residual has
+// dropped by GMRES_TOL or after max_inner vectors.  Every vector operation
+// runs on the device; the host reads back j + 2 numbers per inner step.
+constexpr double GMRES_TOL = 1e-6;
+
+extern "C" int luqr_solve_gmres_ir(luqr_factors f, const double *dA, int64_t lda, const double *db, double *dx,
+                                   int32_t max_outer, int32_t max_inner, int32_t *inner_total, void *stream) {
+    if (!f) return -1;
+    if (!dA) return -2;
+    if (lda < f->L.N) return -3;
+    if (!db) return -4;
+    if (!dx) return -5;
+    if (max_outer < 0) return -6;
+    if (max_inner < 1 || max_inner > KRYLOV_MAX) return -7;
+    if (f->nsteps < f->L.n) return LUQR_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    const Layout &L = f->L;
+    const int *hdec;
+    int rc0 = host_decisions(f, &hdec);
+    if (rc0) return rc0;
+    char *b = (char *)f->base;
+    const int64_t N = L.N, Np = L.Np;
+    int *conv = (int *)(b + L.off_conv);
+    double *R = (double *)(b + L.off_R);      // residual, or -A v for a basis vector v
+    double *Z0 = (double *)(b + L.off_D);     // zeros: the right-hand side of a plain product A v
+    double *X = (double *)(b + L.off_Xd);     // iterate
+    double *part = (double *)(b + L.off_part);
+    double *apart = (double *)(b + L.off_apart);
+    double *norms = (double *)(b + L.off_rnorm);
+    double *V = (double *)(b + L.off_kry);    // basis V_0 .. V_m (Np apart)
+    double *W = V + (size_t)(KRYLOV_MAX + 1) * Np;
+    double *dpart = (double *)(b + L.off_kdots);
+    double *h1 = dpart + (KRYLOV_MAX + 1) * DOT_BLOCKS;
+    double *h2 = h1 + (KRYLOV_MAX + 1);
+    double *nrm = h2 + (KRYLOV_MAX + 1);
+    double *ycoef = nrm + 2;
+    const unsigned vb = nblk(Np);
+    const dim3 rgrid(nblk(N), (unsigned)L.nparts, 1);
+    const dim3 rgrid_final(nblk(N));
+    SolveArgs s = solve_args(f, 1, nullptr);
+    hipError_t e = hipSuccess;
+    auto precond = [&](const double *src, int64_t ld, double *dst) {  // dst = M^{-1} src
+        k_rhs_in<<<vb, WG, 0, st>>>(src, ld, s.Y, N, Np, 1, nullptr);
+        f->ops->solve(f->c, L, s, hdec, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dst, s.X, Np * sizeof(double), hipMemcpyDeviceToDevice, st);
+    };
+    auto dots = [&](const double *Vb, int nv, const double *w, double *out) {  // out[i] = V_i . w
+        k_dots_part<<<dim3(DOT_BLOCKS, nv), WG, 0, st>>>(Vb, Np, w, Np, dpart);
+        k_dots_final<<<1, 64, 0, st>>>(dpart, nv, out);
+    };
+    auto fetch = [&](double *host, const double *dev, size_t count) {
+        if (e == hipSuccess) e = hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    };
+    (void)hipGetLastError();
+    k_ir_reset<<<1, 64, 0, st>>>(f->c.st, conv);
+    k_fill_f64<<<1, 64, 0, st>>>(norms, 3);
+    k_fill_f64<<<vb, WG, 0, st>>>(Z0, Np);
+    precond(db, N, X);  // x_0 = M^{-1} b
+    const int m = max_inner;
+    std::vector<double> Hc((size_t)m * (m + 1)), g(m + 1), cs(m), sn(m), y(m), hb(2 * (KRYLOV_MAX + 1) + 1);
+    int inner = 0;
+    for (int outer = 0;; ++outer) {
+        const bool last = outer == max_outer;
+        k_fill_f64<<<1, 64, 0, st>>>(norms, 2);  // keep ||A|| (slot 2) once known
+        k_resid_part<<<rgrid, WG, 0, st>>>(dA, lda, N, Np, X, 1, part, outer == 0 ? apart : nullptr, nullptr);
+        k_resid_final<<<rgrid_final, WG, 0, st>>>(db, N, N, Np, 1, (int)L.nparts, part,
+                                                  outer == 0 ? apart : nullptr, X, R, norms, nullptr);
+        k_ir_check<<<1, 64, 0, st>>>(norms, 1, N, conv, f->c.st, last ? 1 : 0);
+        int done = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&done, conv, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_rc(e);
+        if (done || last) break;
+        // GMRES(m) on M^{-1} A d = M^{-1} r
+        precond(R, Np, V);
+        dots(V, 1, V, nrm);
+        double beta2 = 0.0;
+        fetch(&beta2, nrm, 1);
+        if (e != hipSuccess) return hip_rc(e);
+        if (!(beta2 > 0.0)) break;
+        const double beta = sqrt(beta2);
+        k_normalize<<<vb, WG, 0, st>>>(V, V, nrm, Np);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int used = 0;
+        for (int j = 0; j < m; ++j) {
+            double *Vj = V + (size_t)j * Np;
+            k_resid_part<<<rgrid, WG, 0, st>>>(dA, lda, N, Np, Vj, 1, part, nullptr, nullptr);
+            k_resid_final<<<rgrid_final, WG, 0, st>>>(Z0, Np, N, Np, 1, (int)L.nparts, part, nullptr, Vj, R, norms,
+                                                      nullptr);                      // R = -A V_j
+            precond(R, Np, W);                                                   // W = -M^{-1} A V_j
+            k_lincomb<<<vb, WG, 0, st>>>(W, -1.0, V, Np, 0, nullptr, 0.0, Np);   // w = M^{-1} A V_j
+            dots(V, j + 1, W, h1);                                               // two Gram-Schmidt passes
+            k_lincomb<<<vb, WG, 0, st>>>(W, 1.0, V, Np, j + 1, h1, -1.0, Np);
+            dots(V, j + 1, W, h2);
+            k_lincomb<<<vb, WG, 0, st>>>(W, 1.0, V, Np, j + 1, h2, -1.0, Np);
+            dots(W, 1, W, nrm);
+            fetch(hb.data(), h1, 2 * (KRYLOV_MAX + 1) + 1);  // h1, h2, |w|^2 are contiguous
+            if (e != hipSuccess) return hip_rc(e);
+            double *hc = &Hc[(size_t)j * (m + 1)];
+            for (int i = 0; i <= j; ++i) hc[i] = hb[i] + hb[KRYLOV_MAX + 1 + i];
+            const double hn2 = hb[2 * (KRYLOV_MAX + 1)];
+            const double hnext = hn2 > 0.0 ? sqrt(hn2) : 0.0;
+            for (int i = 0; i < j; ++i) {  // earlier rotations
+                const double a0 = cs[i] * hc[i] + sn[i] * hc[i + 1];
+                hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+                hc[i] = a0;
+            }
+            const double rr = hypot(hc[j], hnext);
+            cs[j] = rr > 0.0 ? hc[j] / rr : 1.0;
+            sn[j] = rr > 0.0 ? hnext / rr : 0.0;
+            hc[j] = rr;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            used = j + 1;
+            if (!(hnext > 0.0) || fabs(g[j + 1]) <= GMRES_TOL * beta) break;
+            if (j + 1 < m) k_normalize<<<vb, WG, 0, st>>>(V + (size_t)(j + 1) * Np, W, nrm, Np);
+        }
+        inner += used;
+        for (int i = used - 1; i >= 0; --i) {  // y = H^{-1} g (upper triangular after the rotations)
+            double acc = g[i];
+            for (int k2 = i + 1; k2 < used; ++k2) acc -= Hc[(size_t)k2 * (m + 1) + i] * y[k2];
+            y[i] = Hc[(size_t)i * (m + 1) + i] != 0.0 ? acc / Hc[(size_t)i * (m + 1) + i] : 0.0;
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(ycoef, y.data(), used * sizeof(double), hipMemcpyHostToDevice, st);
+        k_lincomb<<<vb, WG, 0, st>>>(X, 1.0, V, Np, used, ycoef, 1.0, Np);  // x += V y
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // y is read before it goes out of scope
+        if (e != hipSuccess) return hip_rc(e);
+    }
+    if (inner_total) *inner_total = inner;
+    k_rhs_out<<<nblk(N), WG, 0, st>>>(X, dx, N, N, Np, 1);
     return hip_rc(hipGetLastError());
 }
 

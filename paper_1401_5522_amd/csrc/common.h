@@ -15,6 +15,7 @@ namespace lq {
 constexpr int WG = 256;    // threads per workgroup
 constexpr int IB = 16;     // inner block of panel factorizations and compact-WY factors
 constexpr int WAVE = 64;
+constexpr int KRYLOV_MAX = 30;  // largest GMRES basis of luqr_solve_gmres_ir
 
 enum Prec { P64 = 0, P32 = 1, PB16 = 2 };
 
@@ -240,6 +241,7 @@ struct Layout {
     size_t off_dec, off_s, off_m, off_margin, off_status;
     size_t off_tnorm, off_away, off_lmax, off_invpart, off_flags, off_scale;
     size_t off_Y, off_Z, off_X, off_R, off_D, off_Xd, off_G, off_part, off_apart, off_rnorm, off_anorm, off_conv;
+    size_t off_kry, off_kdots;  // GMRES refinement: KRYLOV_MAX + 2 vectors of Np doubles; dot scratch
     size_t total;
     int64_t nparts;  // column chunks of the residual kernel
 };
@@ -288,6 +290,8 @@ inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max) {
     L.off_rnorm = take(r * 4 * 8);
     L.off_anorm = take(8);
     L.off_conv = take(16);
+    L.off_kry = take(Np * (KRYLOV_MAX + 2) * 8);
+    L.off_kdots = take((KRYLOV_MAX + 2) * (64 + 4) * 8);
     L.total = o;
     return L;
 }

@@ -80,6 +80,16 @@ class Factors:
                              max_iter, _stream())
         return X[:, 0] if vec else X
 
+    def solve_gmres_ir(self, A: torch.Tensor, b: torch.Tensor, max_outer=10, max_inner=30):
+        """GMRES-based refinement of one right-hand side; returns (x, inner
+        steps)."""
+        A = colmajor(A)
+        bc = b.reshape(-1).to(device="cuda", dtype=torch.float64).contiguous()
+        x = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        inner = L.luqr_solve_gmres_ir(self.h, C.c_void_p(A.data_ptr()), self.N, C.c_void_p(bc.data_ptr()),
+                                      C.c_void_p(x.data_ptr()), max_outer, max_inner, _stream())
+        return x, inner
+
     def decisions(self):
         n = self.n
         dec = np.zeros(n, np.int8)

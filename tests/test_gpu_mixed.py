@@ -185,3 +185,28 @@ def test_refinement_status_with_many_rhs(gpu, nrhs):
     # at this level both residuals are rounding noise of differently ordered
     # FP64 sums; stale norms gave values off by orders of magnitude (or 0)
     assert 0.5 * eta.max() <= st.ir_eta <= 2.0 * eta.max(), (st.ir_eta, eta.max())
+
+
+@pytest.mark.parametrize("prec,kappa,nb", [("fp32", 1e8, 128), ("bf16", 1e4, 512)])
+def test_gmres_refinement(gpu, prec, kappa, nb):
+    """GMRES-based refinement reaches the FP64 backward-error target where the
+    factors are too inaccurate for plain refinement to contract (FP32 factors
+    of a kappa = 1e8 matrix: kappa u_32 > 1), and agrees with a dense FP64
+    solve to what the conditioning allows."""
+    import torch
+    N = 1536
+    A = inputs.usv(N, kappa, seed=(119, N))
+    b = inputs.rhs(N, 1, seed=(120, N)).reshape(-1)
+    Ad = torch.from_numpy(A).cuda()
+    bd = torch.from_numpy(b).cuda()
+    f = gpu.factor(Ad, nb, criterion="max", alpha=1e4, precision=prec)
+    x, inner = f.solve_gmres_ir(Ad, bd, max_outer=10, max_inner=30)
+    st = f.status()
+    assert st.watchdog == 0
+    assert st.ir_converged == 1, (st.ir_iters, st.ir_eta, inner)
+    x = x.cpu().numpy()
+    e = eta(A, x, b)
+    assert e <= N * 1e-16 and st.ir_eta <= N * 1e-16, (e, st.ir_eta)
+    xo = np.linalg.solve(A, b)
+    cond = np.linalg.cond(A, np.inf)
+    assert np.abs(x - xo).max() / np.abs(xo).max() <= 4 * cond * N * 1e-16
