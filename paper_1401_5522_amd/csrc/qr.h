@@ -32,6 +32,10 @@ namespace lq {
 
 template <class S> LQ_DEV S sq(S x) { return x * x; }
 
+// x = hi + lo to about 2^-16 relative, hi and lo rounded to BF16.
+LQ_DEV __bf16 bf_hi(float x) { return (__bf16)x; }
+LQ_DEV __bf16 bf_lo(float x) { return (__bf16)(x - (float)(__bf16)x); }
+
 template <int NB> constexpr int qr_rpt() { return NB > 256 ? 2 : 1; }  // panel rows per thread
 
 // ---------------------------------------------------------------------------
@@ -226,10 +230,10 @@ LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
 // Ys holds both LDS copies of V (put_v), Ts[q*IB + p] = T(p, q).
 // W = V^T bot accumulates in two independent chains (even and odd row
 // blocks); the top rows are added afterwards, so their load is off the chain.
-// PRE (one workgroup per CU): every V operand of both phases is read before
-// the first MFMA.  Otherwise (two workgroups per CU, half the registers) each
-// 128-bit operand is read just before its MFMAs and the other workgroup
-// covers the latency.
+// PRE: every V operand of both phases is read before the first MFMA (the
+// batched kernel's 32/64 tiles).  Otherwise (k_qr_step: at nb >= 256 the bulk
+// loads would exceed the registers) each 128-bit operand is read just before
+// its MFMAs, and a second workgroup on the CU covers the latency.
 // ---------------------------------------------------------------------------
 template <int NB, int P, bool HAS_TOP, bool PRE = true>
 LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *top, int b,
@@ -291,20 +295,27 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *
                                                 Wc[rb & 1][qb]);
     } else {
 #pragma unroll
+        // three-term split: x = hi + lo with hi, lo in BF16, and the product
+        // as hi.hi + hi.lo + lo.hi (the dropped lo.lo term is 2^-16 relative):
+        // every block application would otherwise perturb the tile by the
+        // BF16 rounding of its operands, and a tile receives one per block
+        // of every panel tile below it
         for (int pr = 0; pr < NB / 32; ++pr) {
-            bf8 bo;
+            bf8 bh, bl;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) bo[e] = (__bf16)bot[2 * pr + (e >> 2)][e & 3];
+            for (int e = 0; e < 8; ++e) { const float xs_ = bot[2 * pr + (e >> 2)][e & 3]; bh[e] = bf_hi(xs_); bl[e] = bf_lo(xs_); }
 #pragma unroll
             for (int qb = 0; qb < NQ; ++qb) {
-                const f4 lo = vw(qb, 2 * pr), hi = vw(qb, 2 * pr + 1);
-                bf8 a;
+                const f4 v0 = vw(qb, 2 * pr), v1 = vw(qb, 2 * pr + 1);
+                bf8 ah, al;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    a[e] = (__bf16)lo[e];
-                    a[4 + e] = (__bf16)hi[e];
+                    { const float xs_ = v0[e]; ah[e] = bf_hi(xs_); al[e] = bf_lo(xs_); }
+                    { const float xs_ = v1[e]; ah[4 + e] = bf_hi(xs_); al[4 + e] = bf_lo(xs_); }
                 }
-                Wc[pr & 1][qb] = Tr<PB16>::mma(a, bo, Wc[pr & 1][qb]);
+                Wc[pr & 1][qb] = Tr<PB16>::mma(ah, bh, Wc[pr & 1][qb]);
+                Wc[pr & 1][qb] = Tr<PB16>::mma(ah, bl, Wc[pr & 1][qb]);
+                Wc[pr & 1][qb] = Tr<PB16>::mma(al, bh, Wc[pr & 1][qb]);
             }
         }
     }
@@ -355,21 +366,24 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *
                 for (int rb = 0; rb < RB; ++rb)
                     bot[rb] = Tr<P>::mma(Yr[(16 * rb + i16) * LDQ + 16 * ob + Tr<P>::drow(g, r)], Wp[ob][r], bot[rb]);
     } else {
-        // K = 32 per MFMA; a 16-reflector block fills the second half with zeros
-        bf8 bw;
+        // K = 32 per MFMA (a 16-reflector block fills the second half with
+        // zeros); the same three-term split as above
+        bf8 wh, wl;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bw[e] = (e >> 2) < NQ ? (__bf16)Wp[(e >> 2) % NQ][e & 3] : (__bf16)0.0f;
+        for (int e = 0; e < 8; ++e) { const float xs_ = (e >> 2) < NQ ? Wp[(e >> 2) % NQ][e & 3] : 0.0f; wh[e] = bf_hi(xs_); wl[e] = bf_lo(xs_); }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            bf8 a;
+            bf8 ah, al;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
                 if (h < NQ) v = vu(h, rb);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) a[4 * h + e] = (__bf16)v[e];
+                for (int e = 0; e < 4; ++e) { const float xs_ = v[e]; ah[4 * h + e] = bf_hi(xs_); al[4 * h + e] = bf_lo(xs_); }
             }
-            bot[rb] = Tr<PB16>::mma(a, bw, bot[rb]);
+            bot[rb] = Tr<PB16>::mma(ah, wh, bot[rb]);
+            bot[rb] = Tr<PB16>::mma(ah, wl, bot[rb]);
+            bot[rb] = Tr<PB16>::mma(al, wh, bot[rb]);
         }
     }
 }
