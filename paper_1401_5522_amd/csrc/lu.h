@@ -54,7 +54,7 @@ __global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
         const double *Ui = c.Dinv + (size_t)k * NB * NB;
         typename Tr<P>::acc acc[RB / WM / 16][NB / WN / 16];
         acc_zero<P, RB, NB, WM, WN>(acc);
-        wg_mma<P, RB, NB, WM, WN, BK>(
+        wg_mma_split<P, RB, NB, WM, WN, BK>(
             acc, NB, [&](int r, int kk) { return (double)X[r0 + r + kk * NB]; },
             [&](int kk, int cc) { return Ui[kk + (size_t)cc * NB]; }, smem);
         __syncthreads();
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
         const int *pm = c.perm + (size_t)k * NB;
         typename Tr<P>::acc acc[NB / WN / 16][RB / WM / 16];
         acc_zero<P, NB, RB, WN, WM>(acc);
-        wg_mma<P, NB, RB, WN, WM, BK>(
+        wg_mma_split<P, NB, RB, WN, WM, BK>(
             acc, NB, [&](int r, int kk) { return Li[r + (size_t)kk * NB]; },
             [&](int kk, int cc) { return (double)X[pm[kk] + (c0 + cc) * NB]; }, smem);
         __syncthreads();
@@ -95,9 +95,9 @@ __global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
 }
 
 // Update: A_ij -= A_ik A_kj over the (n-k-1)^2 trailing tiles, BT x BT
-// output blocks per workgroup.  BF16 mode: operands are rounded to bf16
-// after scaling each tile by a power of two (its max |a| in [1,2)), the
-// product accumulates in FP32 and is scaled back exactly.
+// output blocks per workgroup.  BF16 mode: each tile is scaled by a power of
+// two (its max |a| in [1,2)), the operands are split into bf16 hi + lo terms
+// (wg_mma_split), the product accumulates in FP32 and is scaled back exactly.
 template <int NB> constexpr int upd_bt() { return NB >= 128 ? 128 : NB; }
 
 // FP32 storage, nb >= 128: a dedicated 128 x 128 x nb tile product.
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(WG, (upd_occ<P>())) void k_lu_update(Ctx c, int k, 
     const float sa = tile_scale<P>(c, i, k), sb = tile_scale<P>(c, k, j);
     typename Tr<P>::acc acc[BT / 2 / 16][BT / 2 / 16];
     acc_zero<P, BT, BT, 2, 2>(acc);
-    wg_mma<P, BT, BT, 2, 2, BK>(
+    wg_mma_split<P, BT, BT, 2, 2, BK>(
         acc, NB, [&](int r, int kk) { return (double)Aik[r0 + r + kk * NB] * sa; },
         [&](int kk, int cc) { return (double)Akj[kk + (c0 + cc) * NB] * sb; }, smem);
     const double inv = 1.0 / ((double)sa * (double)sb);

@@ -104,4 +104,24 @@ LQ_DEV void acc_zero(typename Tr<P>::acc (&acc)[BM / WM / 16][BN / WN / 16]) {
         for (int nb = 0; nb < Sh::NBK; ++nb) acc[mb][nb] = zero_acc<typename Tr<P>::acc>();
 }
 
+// wg_mma with BF16 operands split in two terms, x = hi + lo with hi = bf16(x)
+// and lo = bf16(x - hi): acc += Ah Bh + Ah Bl + Al Bh.  The dropped Al Bl term
+// and the rounding of lo leave a relative operand error near 2^-16 instead
+// of 2^-8, at three times the MFMA work.  Other precisions take one pass.
+template <int P, int BM, int BN, int WM, int WN, int BK, class FA, class FB>
+LQ_DEV void wg_mma_split(typename Tr<P>::acc (&acc)[BM / WM / 16][BN / WN / 16], int K, FA fa, FB fb, void *smem) {
+    if constexpr (P != PB16) {
+        wg_mma<P, BM, BN, WM, WN, BK>(acc, K, fa, fb, smem);
+    } else {
+        auto hi = [](double x) { return (double)(float)(__bf16)(float)x; };
+        auto ah = [&](int r, int k) { return hi(fa(r, k)); };
+        auto bh = [&](int k, int c) { return hi(fb(k, c)); };
+        auto al = [&](int r, int k) { const double x = fa(r, k); return x - hi(x); };
+        auto bl = [&](int k, int c) { const double x = fb(k, c); return x - hi(x); };
+        wg_mma<P, BM, BN, WM, WN, BK>(acc, K, ah, bh, smem);
+        wg_mma<P, BM, BN, WM, WN, BK>(acc, K, ah, bl, smem);
+        wg_mma<P, BM, BN, WM, WN, BK>(acc, K, al, bh, smem);
+    }
+}
+
 }  // namespace lq
