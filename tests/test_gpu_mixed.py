@@ -210,3 +210,31 @@ def test_gmres_refinement(gpu, prec, kappa, nb):
     xo = np.linalg.solve(A, b)
     cond = np.linalg.cond(A, np.inf)
     assert np.abs(x - xo).max() / np.abs(xo).max() <= 4 * cond * N * 1e-16
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_lu_contraction_accuracy(gpu, prec):
+    """All-LU factorization (forced sequence, Alg. 1 with every step LU) of a
+    dense kappa = 1e2 matrix: every trailing entry receives seven Schur
+    updates whose products are of the size of the entries.  With the
+    two-term BF16 operand split the factor error is near 2^-16 relative
+    instead of 2^-8.  Each refinement pass shrinks the error by about
+    kappa x growth x that factor error, here near 1e-2, so the storage-precision
+    solve reaches N 1e-16 within a few passes; with single-rounded BF16
+    operands the factor is 256 times larger and the passes barely contract."""
+    import torch
+    N, nb = 2048, 256
+    A = inputs.usv(N, 1e2, seed=(117, N))
+    b = inputs.rhs(N, 1, seed=(118, N)).reshape(-1)
+    Ad = torch.from_numpy(A).cuda()
+    bd = torch.from_numpy(b).cuda()
+    f = gpu.factor(Ad, nb, criterion="forced", forced=np.ones(N // nb, np.int8), precision=prec)
+    x = f.solve_refined(Ad, bd, max_iter=40).cpu().numpy()
+    st = f.status()
+    print(prec, "iters", st.ir_iters, "eta", st.ir_eta)
+    assert st.watchdog == 0
+    assert (f.decisions()[0] == 1).all()  # 1 = LU
+    target = N * 1e-16
+    assert st.ir_converged == 1, (st.ir_iters, st.ir_eta)
+    assert st.ir_eta <= target and eta(A, x, b) <= target
+    assert st.ir_iters <= 8, (st.ir_iters, st.ir_eta)
