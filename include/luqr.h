@@ -71,7 +71,6 @@ typedef struct {
     const int8_t *forced;/* host pointer, n = ceil(N/nb) decisions, read by luqr_factor (FORCED only) */
     int32_t nsteps;      /* run only the first nsteps panel steps (< 0: all); a partial
                             factorization cannot be solved with */
-    int32_t mumps_reading; /* 0 (default): estimate_max(j) = away_max(j) * prod_{i<j} growth(i) */
     int32_t timing;      /* nonzero: record HIP events between the kernels of each step
                             (read back with luqr_get_step_times) */
     int32_t no_lookahead;/* 0 (default): lookahead (the Sec. 4 task graph's overlap of

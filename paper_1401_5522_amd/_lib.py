@@ -25,7 +25,7 @@ EXPORTED = ["luqr_workspace_bytes", "luqr_factor", "luqr_solve", "luqr_solve_ref
 class luqr_opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("criterion", C.c_int32), ("alpha", C.c_double),
                 ("precision", C.c_int32), ("nrhs_max", C.c_int32), ("seed", C.c_uint64),
-                ("forced", C.POINTER(C.c_int8)), ("nsteps", C.c_int32), ("mumps_reading", C.c_int32),
+                ("forced", C.POINTER(C.c_int8)), ("nsteps", C.c_int32),
                 ("timing", C.c_int32), ("no_lookahead", C.c_int32)]
 
 
@@ -99,7 +99,7 @@ def lib() -> C.CDLL:
 
 
 def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed=0, forced=None,
-              nsteps=-1, mumps_reading=0, timing=False, lookahead=True):
+              nsteps=-1, timing=False, lookahead=True):
     o = luqr_opts()
     o.nb = int(nb)
     o.criterion = CRITERIA[criterion] if isinstance(criterion, str) else int(criterion)
@@ -112,7 +112,6 @@ def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed
         keep = (C.c_int8 * len(forced))(*[int(v) for v in forced])
         o.forced = C.cast(keep, C.POINTER(C.c_int8))
     o.nsteps = int(nsteps)
-    o.mumps_reading = int(mumps_reading)
     o.timing = 1 if timing else 0
     o.no_lookahead = 0 if lookahead else 1
     return o, keep

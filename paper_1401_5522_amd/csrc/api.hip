@@ -60,7 +60,6 @@ static int check_opts(int64_t N, const luqr_opts *o, int pos_opts) {
     if (o->criterion < 0 || o->criterion > 4) return -pos_opts;
     if (o->precision < 0 || o->precision > 2) return -pos_opts;
     if (o->criterion == LUQR_CRIT_FORCED && !o->forced) return -pos_opts;
-    if (o->mumps_reading < 0 || o->mumps_reading > 2) return -pos_opts;
     if (!pick_ops(o->nb, o->precision)) return LUQR_ERR_UNSUPPORTED;
     (void)N;
     return 0;
@@ -118,13 +117,13 @@ extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_
     return 0;
 }
 
-static SolveArgs solve_args(luqr_factors f, int nrhs, const int *gate) {
-    char *b = (char *)f->base;
+static SolveArgs solve_args(const Layout &L, void *base, int nrhs, const int *gate) {
+    char *b = (char *)base;
     SolveArgs s;
-    s.Y = (double *)(b + f->L.off_Y);
-    s.Z = (double *)(b + f->L.off_Z);
-    s.X = (double *)(b + f->L.off_X);
-    s.G = (double *)(b + f->L.off_G);
+    s.Y = (double *)(b + L.off_Y);
+    s.Z = (double *)(b + L.off_Z);
+    s.X = (double *)(b + L.off_X);
+    s.G = (double *)(b + L.off_G);
     s.nrhs = nrhs;
     s.gate = gate;
     return s;
@@ -140,13 +139,65 @@ extern "C" int luqr_solve(luqr_factors f, int64_t nrhs, double *dB, int64_t ldb,
     const int *hdec;
     int rc = host_decisions(f, &hdec);
     if (rc) return rc;
-    SolveArgs s = solve_args(f, (int)nrhs, nullptr);
+    SolveArgs s = solve_args(f->L, f->base, (int)nrhs, nullptr);
     (void)hipGetLastError();
     k_rhs_in<<<nblk(f->L.Np * nrhs), WG, 0, st>>>(dB, ldb, s.Y, f->L.N, f->L.Np, (int)nrhs, nullptr);
     f->ops->solve(f->c, f->L, s, hdec, st);
     k_rhs_out<<<nblk(f->L.N * nrhs), WG, 0, st>>>(s.X, dB, ldb, f->L.N, f->L.Np, (int)nrhs);
     return hip_rc(hipGetLastError());
 }
+
+// The body of luqr_solve_refined over a factorization in the workspace at
+// `base` whose decision sequence the host holds in hdec.
+static int refined_solve(const Layout &L, const Ctx &c, const Ops *ops, void *base, const int *hdec,
+                         const double *dA, int64_t lda, int64_t nrhs, const double *dB, int64_t ldb, double *dX,
+                         int64_t ldx, int32_t max_iter, hipStream_t st) {
+    char *b = (char *)base;
+    int *conv = (int *)(b + L.off_conv);
+    double *R = (double *)(b + L.off_R);
+    double *D = (double *)(b + L.off_D);
+    double *Xk = (double *)(b + L.off_Xd);
+    double *part = (double *)(b + L.off_part);
+    double *norms = (double *)(b + L.off_rnorm);
+    double *apart = (double *)(b + L.off_apart);
+    const int nq = (int)nrhs;
+    const int64_t total = L.Np * nrhs;
+    (void)hipGetLastError();
+    k_ir_reset<<<1, 64, 0, st>>>(c.st, conv);
+    k_fill_f64<<<nblk(2 * nrhs + 1), WG, 0, st>>>(norms, 2 * nrhs + 1);  // ||r||, ||x|| per column, ||A||
+    // x0 = solve(b): solve writes its result into X; keep the iterate in Xk
+    SolveArgs s = solve_args(L, base, nq, nullptr);
+    k_rhs_in<<<nblk(total), WG, 0, st>>>(dB, ldb, s.Y, L.N, L.Np, nq, nullptr);
+    ops->solve(c, L, s, hdec, st);
+    hipError_t ce = hipMemcpyAsync(Xk, s.X, total * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (ce != hipSuccess) return hip_rc(ce);
+    const dim3 rgrid(nblk(L.N), (unsigned)L.nparts, (unsigned)((nq + RQR - 1) / RQR));
+    const dim3 rgrid_final(nblk(L.N * nrhs));
+    for (int it = 0; it <= max_iter; ++it) {
+        const bool last = it == max_iter;
+        k_resid_part<<<rgrid, WG, 0, st>>>(dA, lda, L.N, L.Np, Xk, nq, part, it == 0 ? apart : nullptr, conv);
+        k_resid_final<<<rgrid_final, WG, 0, st>>>(dB, ldb, L.N, L.Np, nq, (int)L.nparts, part,
+                                                  it == 0 ? apart : nullptr, Xk, R, norms, conv);
+        k_ir_check<<<1, 64, 0, st>>>(norms, nq, L.N, conv, c.st, last ? 1 : 0);
+        if (last) break;
+        // stop enqueuing once the test has passed (one small read per iteration)
+        int done = 0;
+        hipError_t ce2 = hipMemcpyAsync(&done, conv, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (ce2 == hipSuccess) ce2 = hipStreamSynchronize(st);
+        if (ce2 != hipSuccess) return hip_rc(ce2);
+        if (done) break;
+        SolveArgs sr = solve_args(L, base, nq, conv);
+        // rows N..Np-1 of R are never written by the residual kernels: copy
+        // only the first N rows and zero the padding
+        k_rhs_in<<<nblk(total), WG, 0, st>>>(R, L.Np, sr.Y, L.N, L.Np, nq, conv);
+        sr.X = D;
+        ops->solve(c, L, sr, hdec, st);
+        k_ir_update<<<nblk(total), WG, 0, st>>>(Xk, D, total, conv);
+    }
+    k_rhs_out<<<nblk(L.N * nrhs), WG, 0, st>>>(Xk, dX, ldx, L.N, L.Np, nq);
+    return hip_rc(hipGetLastError());
+}
+
 
 extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda, int64_t nrhs, const double *dB,
                                   int64_t ldb, double *dX, int64_t ldx, int32_t max_iter, void *stream) {
@@ -160,53 +211,11 @@ extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda,
     if (ldx < f->L.N) return -8;
     if (max_iter < 0) return -9;
     if (f->nsteps < f->L.n) return LUQR_ERR_UNSUPPORTED;
-    hipStream_t st = (hipStream_t)stream;
-    const Layout &L = f->L;
     const int *hdec;
     int rc0 = host_decisions(f, &hdec);
     if (rc0) return rc0;
-    char *b = (char *)f->base;
-    int *conv = (int *)(b + L.off_conv);
-    double *R = (double *)(b + L.off_R);
-    double *D = (double *)(b + L.off_D);
-    double *Xk = (double *)(b + L.off_Xd);
-    double *part = (double *)(b + L.off_part);
-    double *norms = (double *)(b + L.off_rnorm);
-    double *apart = (double *)(b + L.off_apart);
-    const int nq = (int)nrhs;
-    const int64_t total = L.Np * nrhs;
-    (void)hipGetLastError();
-    k_ir_reset<<<1, 64, 0, st>>>(f->c.st, conv);
-    k_fill_f64<<<nblk(2 * nrhs + 1), WG, 0, st>>>(norms, 2 * nrhs + 1);  // ||r||, ||x|| per column, ||A||
-    // x0 = solve(b): solve writes its result into X; keep the iterate in Xk
-    SolveArgs s = solve_args(f, nq, nullptr);
-    k_rhs_in<<<nblk(total), WG, 0, st>>>(dB, ldb, s.Y, L.N, L.Np, nq, nullptr);
-    f->ops->solve(f->c, L, s, hdec, st);
-    hipError_t ce = hipMemcpyAsync(Xk, s.X, total * sizeof(double), hipMemcpyDeviceToDevice, st);
-    if (ce != hipSuccess) return hip_rc(ce);
-    const dim3 rgrid(nblk(L.N), (unsigned)L.nparts, (unsigned)((nq + RQR - 1) / RQR));
-    const dim3 rgrid_final(nblk(L.N * nrhs));
-    for (int it = 0; it <= max_iter; ++it) {
-        const bool last = it == max_iter;
-        k_resid_part<<<rgrid, WG, 0, st>>>(dA, lda, L.N, L.Np, Xk, nq, part, it == 0 ? apart : nullptr, conv);
-        k_resid_final<<<rgrid_final, WG, 0, st>>>(dB, ldb, L.N, L.Np, nq, (int)L.nparts, part,
-                                                  it == 0 ? apart : nullptr, Xk, R, norms, conv);
-        k_ir_check<<<1, 64, 0, st>>>(norms, nq, L.N, conv, f->c.st, last ? 1 : 0);
-        if (last) break;
-        // stop enqueuing once the test has passed (one small read per iteration)
-        int done = 0;
-        hipError_t ce2 = hipMemcpyAsync(&done, conv, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (ce2 == hipSuccess) ce2 = hipStreamSynchronize(st);
-        if (ce2 != hipSuccess) return hip_rc(ce2);
-        if (done) break;
-        SolveArgs sr = solve_args(f, nq, conv);
-        k_rhs_in<<<nblk(total), WG, 0, st>>>(R, L.Np, sr.Y, L.Np, L.Np, nq, conv);
-        sr.X = D;
-        f->ops->solve(f->c, L, sr, hdec, st);
-        k_ir_update<<<nblk(total), WG, 0, st>>>(Xk, D, total, conv);
-    }
-    k_rhs_out<<<nblk(L.N * nrhs), WG, 0, st>>>(Xk, dX, ldx, L.N, L.Np, nq);
-    return hip_rc(hipGetLastError());
+    return refined_solve(f->L, f->c, f->ops, f->base, hdec, dA, lda, nrhs, dB, ldb, dX, ldx, max_iter,
+                         (hipStream_t)stream);
 }
 
 // GMRES-based iterative refinement (one right-hand side).  Outer loop in
@@ -254,7 +263,7 @@ extern "C" int luqr_solve_gmres_ir(luqr_factors f, const double *dA, int64_t lda
     const unsigned vb = nblk(Np);
     const dim3 rgrid(nblk(N), (unsigned)L.nparts, 1);
     const dim3 rgrid_final(nblk(N));
-    SolveArgs s = solve_args(f, 1, nullptr);
+    SolveArgs s = solve_args(f->L, f->base, 1, nullptr);
     hipError_t e = hipSuccess;
     auto precond = [&](const double *src, int64_t ld, double *dst) {  // dst = M^{-1} src
         k_rhs_in<<<vb, WG, 0, st>>>(src, ld, s.Y, N, Np, 1, nullptr);

@@ -62,7 +62,6 @@ struct Eng {
             a.alpha = o.alpha;
             a.forced_k = (o.criterion == LUQR_CRIT_FORCED) ? o.forced[k] : 0;
             a.seed = o.seed;
-            a.mumps_reading = o.mumps_reading;
             k_panel_decide<NB><<<1, WG, 0, st>>>(c, k, a);
             if (ev) (void)hipEventRecord(ev[E * k + 1], st);
             if (side && k > 0) (void)hipStreamWaitEvent(st, side->eb, 0);  // step k-1's bulk work

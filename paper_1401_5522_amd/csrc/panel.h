@@ -413,7 +413,6 @@ struct DecideArgs {
     double alpha;
     int forced_k;
     unsigned long long seed;
-    int mumps_reading;
 };
 
 // The decision of step k (one workgroup).  Special cases in order: forced
@@ -468,15 +467,15 @@ __global__ __launch_bounds__(WG) void k_panel_decide(Ctx c, int k, DecideArgs a)
             margin = (as - m) / den;
         }
     } else if (a.crit == LUQR_CRIT_MUMPS) {
+        // estimate_max(j) starts at away_max(j) and is multiplied by the
+        // growth factor of every earlier column i < j of the GEPP on the copy
         const double *W = c.W + (size_t)k * NB * NB;
-        double prod_all = 1.0;
-        for (int j = 0; j < mk; ++j) prod_all *= fabs(W[j + j * NB]) / c.lmax[j];
         double prod = 1.0, smin = INFINITY, emax = 0.0;
         lu = 1; margin = INFINITY;
         for (int j = 0; j < mk; ++j) {
             const double pj = fabs(W[j + j * NB]);
             const double gf = pj / c.lmax[j];
-            double est = a.mumps_reading == 1 ? awayj[j] * gf : a.mumps_reading == 2 ? awayj[j] * prod_all : awayj[j] * prod;
+            const double est = awayj[j] * prod;
             prod *= gf;
             if (!isfinite(est) || !isfinite(pj)) nonfinite = 1;
             const double ap = a.alpha * pj;

@@ -72,7 +72,7 @@ template <int NB, class S> LQ_DEV void put_v(S *Ys, int r, int q, S v) {
 }
 
 struct PanelLds {
-    double red[2][IB * 4];  // [buffer][j][wave], holding values of the storage type S
+    double red[2][IB * 4];  // [buffer][j][wave], FP64 partial sums
     double prow[2][IB];     // GEQRT: pivot row of the column being reduced (type S)
 };
 
@@ -83,11 +83,11 @@ LQ_DEV void qr_reduce(S (&P)[qr_rpt<NB>()][IB], int c0, PanelLds *pl) {
     constexpr int RPT = qr_rpt<NB>();
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
     const int pr = c0 + Q;
-    S x[RPT];
+    double x[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int r = tid + 256 * u;
-        x[u] = (TS ? r < NB : (r > pr && r < NB)) ? P[u][Q] : (S)0;
+        x[u] = (TS ? r < NB : (r > pr && r < NB)) ? (double)P[u][Q] : 0.0;
         if (!TS && r == pr) {
 #pragma unroll
             for (int j = 0; j < IB; ++j) ((S *)pl->prow[Q & 1])[j] = P[u][j];
@@ -95,17 +95,17 @@ LQ_DEV void qr_reduce(S (&P)[qr_rpt<NB>()][IB], int c0, PanelLds *pl) {
     }
 #pragma unroll
     for (int half = 0; half < IB / 16; ++half) {
-        S part[16];
+        double part[16];
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
             const int j = 16 * half + jj;
-            S acc = 0;
+            double acc = 0;
 #pragma unroll
-            for (int u = 0; u < RPT; ++u) acc += x[u] * P[u][j];
+            for (int u = 0; u < RPT; ++u) acc += x[u] * (double)P[u][j];
             part[jj] = acc;
         }
-        const S tot = xreduce16<S>(part);
-        if ((l & 3) == 0) ((S *)pl->red[Q & 1])[(16 * half + (l >> 2)) * 4 + w] = tot;
+        const double tot = xreduce16<double>(part);
+        if ((l & 3) == 0) pl->red[Q & 1][(16 * half + (l >> 2)) * 4 + w] = tot;
     }
 }
 
@@ -118,56 +118,60 @@ LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *
     const int tid = threadIdx.x;
     const int pr = c0 + Q;  // GEQRT pivot row
     if (TS && pend_i >= 0) Rb[pend_i] = pend_v;
-    const S *red = (const S *)pl->red[Q & 1];
-    S f[IB];  // x^T a_j: the four waves' partials of column j are adjacent
-#pragma unroll
-    for (int j = 0; j < IB; ++j) f[j] = (red[j * 4] + red[j * 4 + 1]) + (red[j * 4 + 2] + red[j * 4 + 3]);
-    S base[IB];
-#pragma unroll
-    for (int j = 0; j < IB; ++j) {
-        if (TS) base[j] = j >= Q ? Rb[Q * IB + j] : (S)0;  // row q of R (row-major block)
-        else base[j] = ((const S *)pl->prow[Q & 1])[j];
-    }
-    const S ss = f[Q], alpha = base[Q];
-    S tau = 0, beta = alpha, scal = 1;
-    if (ss != (S)0) {
-        const S nrm = sqrt(alpha * alpha + ss);
-        beta = alpha >= (S)0 ? -nrm : nrm;
+    // The sums, the norm and the reflector scalars are FP64 whatever S is: for
+    // 4-byte storage the squares and products of FP32 values can neither
+    // overflow nor underflow in FP64, so no scaling of the column is needed
+    // (the FP32 sums would lose a tail below ~1e-19 and overflow above ~1e19).
+    // f(j) = x^T a_j (the four waves' partials of column j are adjacent);
+    // base(j) = the pivot-row entry (row q of R's row-major block for TS).
+    // Both are re-read from LDS where needed rather than held in registers.
+    const double *red = pl->red[Q & 1];
+    auto f = [&](int j) { return (red[j * 4] + red[j * 4 + 1]) + (red[j * 4 + 2] + red[j * 4 + 3]); };
+    auto base = [&](int j) -> double {
+        if (TS) return j >= Q ? (double)Rb[Q * IB + j] : 0.0;
+        return (double)((const S *)pl->prow[Q & 1])[j];
+    };
+    const double ss = f(Q), alpha = base(Q);
+    double tau = 0, beta = alpha, scal = 1;
+    if (ss != 0.0) {
+        const double nrm = sqrt(alpha * alpha + ss);
+        beta = alpha >= 0.0 ? -nrm : nrm;
         tau = (beta - alpha) / beta;
-        scal = (S)1 / (alpha - beta);
+        scal = 1.0 / (alpha - beta);
     }
-    S d[IB];  // v_q^T a_j (j > q) and v_j^T v_q (j < q)
+    double d[IB];  // v_q^T a_j (j > q) and v_j^T v_q (j < q)
 #pragma unroll
-    for (int j = 0; j < IB; ++j) d[j] = j == Q ? (S)0 : base[j] + scal * f[j];
+    for (int j = 0; j < IB; ++j) d[j] = j == Q ? 0.0 : base(j) + scal * f(j);
     S vq[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int r = tid + 256 * u;
         const bool tail = TS ? r < NB : (r > pr && r < NB);
-        vq[u] = tail ? P[u][Q] * scal : ((!TS && r == pr) ? (S)1 : (S)0);
+        vq[u] = tail ? (S)((double)P[u][Q] * scal) : ((!TS && r == pr) ? (S)1 : (S)0);
         if (tail) P[u][Q] = vq[u];
-        if (!TS && r == pr) P[u][Q] = beta;
+        if (!TS && r == pr) P[u][Q] = (S)beta;
     }
     pend_i = -1;
-    if (TS && tid == 0) { pend_i = Q * IB + Q; pend_v = beta; }
-    if (tau != (S)0) {
+    if (TS && tid == 0) { pend_i = Q * IB + Q; pend_v = (S)beta; }
+    if (tau != 0.0) {
 #pragma unroll
         for (int j = Q + 1; j < IB; ++j) {
-            const S wj = tau * d[j];
+            const double wd = tau * d[j];
+            const S wj = (S)wd;
 #pragma unroll
             for (int u = 0; u < RPT; ++u) P[u][j] -= vq[u] * wj;
-            if (TS && tid == j) { pend_i = Q * IB + j; pend_v = base[j] - wj; }
+            if (TS && tid == j) { pend_i = Q * IB + j; pend_v = (S)(base(j) - wd); }
         }
     }
     // T(0:q, q) = -tau T(0:q, 0:q) G(0:q, q), with G(p, q) = v_p^T v_q = d[p]
     if (tid < Q) {
-        S acc = 0;
+        double acc = 0;
 #pragma unroll
         for (int p = 0; p < Q; ++p)
-            if (p >= tid) acc += Ts[p * IB + tid] * d[p];
-        Ts[Q * IB + tid] = -tau * acc;
+            if (p >= tid) acc += (double)Ts[p * IB + tid] * d[p];
+        Ts[Q * IB + tid] = (S)(-tau * acc);
     } else if (tid < IB) {
-        Ts[Q * IB + tid] = tid == Q ? tau : (S)0;
+        Ts[Q * IB + tid] = tid == Q ? (S)tau : (S)0;
     }
     if constexpr (Q + 1 < IB) {
         qr_reduce<NB, S, TS, Q + 1>(P, c0, pl);

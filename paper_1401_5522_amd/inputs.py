@@ -57,6 +57,22 @@ def kron_example(n, nb, alpha):
     return np.asfortranarray(np.kron(M, np.eye(nb)))
 
 
+def mumps_example(nb=3):
+    """Two tile rows of size nb >= 3 whose first panel separates readings of
+    the MUMPS estimate (Sec. 3.3).  The leading 3 x 3 block of A_00 is
+    [[4, 2, 2], [2, 5, 3], [0, 2, 4]] and the rest of A_00 is 8 I; A_10 holds
+    diag(1, -4, 5) in its leading 3 x 3 block and zeros elsewhere; A_01 = 0
+    and A_11 = 10 I.  The hand computation of the step-0 criterion is written
+    out in the oracle test that uses it."""
+    assert nb >= 3
+    A = np.zeros((2 * nb, 2 * nb))
+    A[:3, :3] = [[4.0, 2.0, 2.0], [2.0, 5.0, 3.0], [0.0, 2.0, 4.0]]
+    A[3:nb, 3:nb] = 8.0 * np.eye(nb - 3)
+    A[nb:nb + 3, :3] = np.diag([1.0, -4.0, 5.0])
+    A[nb:, nb:] = 10.0 * np.eye(nb)
+    return np.asfortranarray(A)
+
+
 def haar(N, g: np.random.Generator):
     """Haar-distributed orthogonal matrix: Q of a Gaussian with diag(R) > 0 (Mezzadri 2007)."""
     Z = g.standard_normal((N, N))

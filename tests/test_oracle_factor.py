@@ -163,6 +163,43 @@ def test_mumps_zero_away_part_is_lu(O):
     assert f.dec.tolist() == [1, 1, 1]
 
 
+# Hand computation for inputs.mumps_example (Sec. 3.3, eq. mumps), step 0:
+#   GEPP on A_00's leading block [[4,2,2],[2,5,3],[0,2,4]]: column 0 pivots on
+#   4 (row 0), multipliers 1/2 and 0, rows 1, 2 become [4, 2] and [2, 4];
+#   column 1 pivots on 4 (row 1), multiplier 1/2, and the last entry becomes
+#   4 - 2/2 = 3.  No interchanges; pivot = (4, 4, 3) (8 on the rest).
+#   local_max = (4, 5, 4), so growth_factor = (1, 4/5, 3/4) (1 on the rest).
+#   away_max = (1, 4, 5) (0 on the rest).
+# The estimate starts at away_max(j) and step i of the GEPP multiplies it by
+# growth_factor(i).  Three readings of which columns step i touches:
+#   chosen, i < j (the columns step i has not yet pivoted): est = (1, 4, 4)
+#   (a) only i = j:                                         est = (1, 3.2, 3.75)
+#   (b) every i:                    est = 0.6 away_max =          (0.6, 2.4, 3)
+# LU iff alpha pivot(j) >= est(j) for all j, i.e. alpha >= max_j est/pivot:
+#   chosen 4/3, (a) 1.25, (b) 1.
+# The margin is min_j (alpha pivot(j) - est(j)) / max(alpha pivot(j), est(j)).
+MUMPS_HAND = {
+    # reading: (m = max est, [(alpha, decision, margin)])
+    0: (4.0, [(1.3, 0, (3.9 - 4.0) / 4.0), (1.4, 1, (4.2 - 4.0) / 4.2)]),
+    1: (3.75, [(1.3, 1, (3.9 - 3.75) / 3.9), (1.2, 0, (3.6 - 3.75) / 3.75)]),
+    2: (3.0, [(1.3, 1, (3.9 - 3.0) / 3.9), (0.9, 0, (2.7 - 3.0) / 3.0)]),
+}
+
+
+@pytest.mark.parametrize("nb", [3, 5])
+def test_mumps_estimate_hand_example(O, nb):
+    A = inputs.mumps_example(nb)
+    for reading, (m, cases) in MUMPS_HAND.items():
+        for alpha, lu, margin in cases:
+            f = O.factor(A, nb, "mumps", alpha, mumps_reading=reading)
+            assert f.dec[0] == lu, (reading, alpha)
+            assert f.s[0] == 3.0                       # smallest pivot
+            assert f.m[0] == pytest.approx(m, rel=1e-15, abs=0), (reading, alpha)
+            assert f.margin[0] == pytest.approx(margin, rel=1e-13), (reading, alpha)
+    # at alpha = 1.3 the chosen reading takes QR while both rejected readings take LU
+    assert [O.factor(A, nb, "mumps", 1.3, mumps_reading=r).dec[0] for r in (0, 1, 2)] == [0, 1, 1]
+
+
 # ---------------------------------------------------------------- solve
 @pytest.mark.parametrize("N,nb", [(12, 4), (14, 4), (9, 3), (16, 4)])
 def test_every_forced_sequence_solves(O, N, nb):
