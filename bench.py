@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--input-cache", default="", metavar="PATH",
                     help="raw FP64 file of A: loaded if it exists, else written after generation (lets "
                          "profiled runs skip the factorizations that build U and V)")
+    ap.add_argument("--dump-steps", default="", metavar="PATH",
+                    help="write the per-step phase durations (mean over the timed steps), decisions and margins "
+                         "of the timed path to PATH as JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -402,6 +405,10 @@ def main():
     roof = roofline(n, nb, prec, dec, times, N)
     phase_ms = {p: round(float(times[:, :, i].sum(axis=1).mean()), 3) for i, p in enumerate(PHASES)}
     fac_ms = float(times.sum(axis=2).sum(axis=1).mean())
+    if args.dump_steps:
+        with open(args.dump_steps, "w") as fh:
+            json.dump({"phases": PHASES, "ms": times.mean(axis=0).tolist(), "dec": dec.tolist(),
+                       "margin": mg.tolist(), "N": N, "nb": nb, "precision": prec, "alpha": args.alpha}, fh)
     del handles, f, X, work
     torch.cuda.empty_cache()
 

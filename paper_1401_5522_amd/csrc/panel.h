@@ -40,6 +40,7 @@ template <int NB> constexpr int lu_rpt() { return NB > 256 ? 2 : 1; }
 struct GetrfLds {
     double bv[4];
     int bi[4];
+    int dnan;  // the diagonal entry of the column being eliminated is NaN
     int piv[32];
     int zp;
     int tcnt;
@@ -61,6 +62,7 @@ LQ_DEV void lu_column(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g) {
             const double a = fabs(P[u][Q]);
             if (a > v) { v = a; idx = r; }
         }
+        if (r == col) g->dnan = P[u][Q] != P[u][Q];
     }
     wave_argmax(v, idx);
     if (l == 0) { g->bv[w] = v; g->bi[w] = idx; }
@@ -73,8 +75,13 @@ LQ_DEV void lu_column(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g) {
         const int oi = g->bi[q];
         if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
     }
-    const bool zero = !(v > 0.0);  // exactly zero (or non-numeric) column: no elimination
-    const int piv = zero ? col : idx;
+    // The scan that defines the pivot starts at the diagonal and moves to a
+    // later row only if its magnitude is strictly larger, so a NaN on the
+    // diagonal stays the pivot (and NaNs below it are never chosen); a column
+    // of exact zeros below and on the diagonal is skipped (no elimination).
+    const bool dnan = g->dnan != 0;
+    const bool zero = !dnan && !(v > 0.0);
+    const int piv = (zero || dnan) ? col : idx;
     if (tid == 0) {
         g->piv[Q] = piv;
         if (zero && g->zp == 0) g->zp = col + 1;
@@ -147,8 +154,13 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
             const int e = e0 + t * WG + tid;
             if (e < NB * NB) W[e] = a[t];
             double m = fabs(a[t]);
-            m = wave_nmax(m);  // a wave covers 64 consecutive rows of one column
-            if (l == 0 && e < NB * NB) atomicMax(&lmx[e / NB], (unsigned long long)__double_as_longlong(m));
+            // non-negative doubles (and NaN above them) order as their bit patterns
+            if constexpr (NB >= 64) {
+                m = wave_nmax(m);  // a wave covers 64 consecutive rows of one column
+                if (l == 0 && e < NB * NB) atomicMax(&lmx[e / NB], (unsigned long long)__double_as_longlong(m));
+            } else if (e < NB * NB) {  // a wave spans several columns: one atomic per element
+                atomicMax(&lmx[e / NB], (unsigned long long)__double_as_longlong(m));
+            }
         }
     }
     __syncthreads();

@@ -74,6 +74,7 @@ CASES = [
     ("diag_dominant", 320, 64, "max", 1.0),     # all LU (block LU without pivoting)
     ("diag_dominant", 320, 64, "sum", 0.5),
     ("gaussian", 320, 64, "mumps", 2.1),
+    ("gaussian", 256, 32, "mumps", 2.1),         # a wave spans two columns of a 32-wide tile
     ("gaussian", 320, 64, "random", 50.0),
     ("growth_prone", 192, 32, "max", 1.0),
     ("gaussian", 1024, 128, "max", 1.0),        # the FP64 N=1024, nb=128 configuration
