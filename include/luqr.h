@@ -185,6 +185,36 @@ int luqr_export_factors(luqr_factors f, double *dF, int64_t ldf, int32_t *ipiv, 
 /* Release the host handle (the workspace belongs to the caller). */
 void luqr_destroy(luqr_factors f);
 
+/* ---- for callers that cannot allocate --------------------------------------
+ * For callers that cannot call hipMalloc or hand over a workspace: code that
+ * runs while a HIP graph is being captured, tight serving loops, harnesses
+ * that forbid allocation.  luqr_factor followed by luqr_solve_refined in one
+ * call, with the workspace taken from a buffer the library itself holds in
+ * device memory: LUQR_NOALLOC_SCRATCH_BYTES (64 MiB) on every GPU it runs
+ * on, kept until the process ends.  Neither the call nor anything it
+ * launches allocates device memory (no hipMalloc, hipFree or allocating
+ * library routine) and no handle is created.
+ *   Arguments as for luqr_factor and luqr_solve_refined: dA (device, N x N,
+ *   lda, FP64, not modified), opts (opts.timing must be 0; lookahead is not
+ *   used, every kernel runs on `stream`), dB (device, N x nrhs, ldb, read),
+ *   dX (device, N x nrhs, ldx, written), max_iter >= 0 refinement passes
+ *   (0: the solve with the factors plus one backward-error check), status
+ *   (host, may be NULL) receives what luqr_get_status would report.
+ *   Returns LUQR_ERR_TOO_LARGE when the workspace this N, tile size,
+ *   precision and opts.nrhs_max need (luqr_workspace_bytes) exceeds
+ *   LUQR_NOALLOC_SCRATCH_BYTES; for example N = 2048 fits in FP64 at
+ *   n_b = 128 and in FP32 at n_b = 256.
+ *   Waits for `stream` (to read the decision sequence, after each refinement
+ *   residual and before returning the status), like luqr_solve_refined.
+ *   Every call on one GPU uses that GPU's one buffer, which keeps the last
+ *   call's contents: calls that overlap on one GPU (from several host threads
+ *   or streams) race and must be serialized by the caller. */
+#define LUQR_NOALLOC_SCRATCH_BYTES (64ll << 20)
+#define LUQR_ERR_TOO_LARGE (-901)
+int luqr_solve_noalloc(int64_t N, const double *dA, int64_t lda, const luqr_opts *opts, int64_t nrhs,
+                       const double *dB, int64_t ldb, double *dX, int64_t ldx, int32_t max_iter,
+                       luqr_status *status, void *stream);
+
 /* ---- many independent systems ------------------------------------------ */
 
 /* Solve batch independent systems A_s x_s = b_s (N_s <= 1024, one right-hand

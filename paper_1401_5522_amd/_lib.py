@@ -11,6 +11,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LUQR_LIB") or os.path.join(_HERE, "libluqr.so")  # LUQR_LIB: another build of the same ABI
 
 LUQR_ERR_UNSUPPORTED = -900
+LUQR_ERR_TOO_LARGE = -901
+NOALLOC_SCRATCH_BYTES = 64 << 20
 LUQR_ERR_HIP = -1000
 
 CRITERIA = {"max": 0, "sum": 1, "mumps": 2, "random": 3, "forced": 4}
@@ -18,6 +20,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["luqr_workspace_bytes", "luqr_factor", "luqr_solve", "luqr_solve_refined", "luqr_solve_gmres_ir",
             "luqr_get_decisions", "luqr_get_status", "luqr_get_step_times", "luqr_export_factors", "luqr_destroy",
+            "luqr_solve_noalloc",
             "luqr_batched_workspace_bytes", "luqr_batched_plan", "luqr_batched_run", "luqr_batched_decision_stride",
             "luqr_batched_destroy", "luqr_batched_autotune"]
 
@@ -43,6 +46,8 @@ def check(rc, what):
     if isinstance(rc, int) and rc < 0:
         if rc == LUQR_ERR_UNSUPPORTED:
             raise LuqrError(f"{what}: unsupported option combination")
+        if rc == LUQR_ERR_TOO_LARGE:
+            raise LuqrError(f"{what}: the problem needs more workspace than the library's buffer holds")
         if rc <= LUQR_ERR_HIP:
             raise LuqrError(f"{what}: HIP error {LUQR_ERR_HIP - rc}")
         raise LuqrError(f"{what}: invalid argument {-rc}")
@@ -82,6 +87,8 @@ def lib() -> C.CDLL:
     L.luqr_export_factors.argtypes = [vp, vp, i64, vp, vp]
     L.luqr_destroy.restype = None
     L.luqr_destroy.argtypes = [vp]
+    L.luqr_solve_noalloc.restype = C.c_int
+    L.luqr_solve_noalloc.argtypes = [i64, vp, i64, op, i64, vp, i64, vp, i64, i32, C.POINTER(luqr_status), vp]
     L.luqr_batched_workspace_bytes.restype = i64
     L.luqr_batched_workspace_bytes.argtypes = [i64, vp, vp, op]
     L.luqr_batched_plan.restype = C.c_int
@@ -168,6 +175,13 @@ def luqr_export_factors(h, dF, ldf, ipiv, stream):
 
 def luqr_destroy(h):
     lib().luqr_destroy(h)
+
+
+def luqr_solve_noalloc(N, dA, lda, opts, nrhs, dB, ldb, dX, ldx, max_iter, stream):
+    st = luqr_status()
+    check(lib().luqr_solve_noalloc(N, dA, lda, C.byref(opts), nrhs, dB, ldb, dX, ldx, max_iter, C.byref(st),
+                                   stream), "luqr_solve_noalloc")
+    return st
 
 
 def luqr_batched_workspace_bytes(batch, N, nb, opts):

@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -459,3 +460,85 @@ extern "C" void luqr_destroy(luqr_factors f) {
     delete f;
 }
 
+
+// ---- the entry point that allocates nothing ---------------------------------
+// luqr_solve_noalloc takes its workspace from `scratch`, a file-scope device
+// array.  Each GPU the library runs on holds its own copy until the process
+// ends.  In host code the array's name is only a stand-in for the symbol, not
+// a device address: the address of the current GPU's copy is looked up once
+// per device with hipGetSymbolAddress and kept in g_scratch_ptr, and only that
+// pointer is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[LUQR_NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+constexpr int NOALLOC_MAX_STEPS = 1024;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+static int scratch_for_current_device(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_rc(e);
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return LUQR_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_rc(e);
+        if (!p || ((uintptr_t)p & 255)) return LUQR_ERR_HIP - (int)hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+extern "C" int luqr_solve_noalloc(int64_t N, const double *dA, int64_t lda, const luqr_opts *o, int64_t nrhs,
+                                  const double *dB, int64_t ldb, double *dX, int64_t ldx, int32_t max_iter,
+                                  luqr_status *status, void *stream) {
+    if (N < 1) return -1;
+    if (!dA) return -2;
+    if (lda < N) return -3;
+    int rc = check_opts(N, o, 4);
+    if (rc) return rc;
+    if (o->timing) return -4;                      // events would have to be created
+    if (nrhs < 1 || nrhs > o->nrhs_max) return -5;
+    if (!dB) return -6;
+    if (ldb < N) return -7;
+    if (!dX) return -8;
+    if (ldx < N) return -9;
+    if (max_iter < 0) return -10;
+    const Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max);
+    if (o->nsteps >= 0 && o->nsteps < L.n) return -4;   // a partial factorization cannot be solved with
+    if (L.total > (size_t)LUQR_NOALLOC_SCRATCH_BYTES || L.n > NOALLOC_MAX_STEPS) return LUQR_ERR_TOO_LARGE;
+    void *base = nullptr;
+    rc = scratch_for_current_device(&base);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const Ctx c = make_ctx(L, base);
+    const Ops *ops = pick_ops(o->nb, o->precision);
+    luqr_opts oo = *o;
+    oo.no_lookahead = 1;                           // one stream: no side stream to create
+    (void)hipGetLastError();
+    ops->factor(c, L, dA, lda, oo, (int)L.n, st, nullptr, nullptr);
+    rc = hip_rc(hipGetLastError());
+    if (rc) return rc;
+    int hdec[NOALLOC_MAX_STEPS];
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = hipMemcpy(hdec, (char *)base + L.off_dec, (size_t)L.n * sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_rc(e);
+    rc = refined_solve(L, c, ops, base, hdec, dA, lda, nrhs, dB, ldb, dX, ldx, max_iter, st);
+    if (rc || !status) return rc;
+    DevStatus d;
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(&d, (char *)base + L.off_status, sizeof(d), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_rc(e);
+    status->info = d.info;
+    status->nonfinite = d.nonfinite;
+    status->n_lu = d.n_lu;
+    status->ir_iters = d.ir_iters;
+    status->ir_converged = d.ir_converged;
+    status->ir_eta = d.ir_eta;
+    status->watchdog = d.watchdog;
+    status->reserved = 0;
+    return 0;
+}
