@@ -78,6 +78,7 @@ constexpr int B_RED = B_VEC + 4 * B_NBMAX * 8;           // reductions
 constexpr int B_LDS = B_RED + WG * 8 + 64;
 
 static_assert(mma_lds_bytes<P32, 64, 64, 16>() <= 9216, "mma staging fits");
+static_assert(qr_vblk<64>() * 4 + 2 * IB * IB * 4 + (int)sizeof(PanelLds) <= 20480, "QR staging fits");
 static_assert(qr_lds<64, P32>() <= 20480, "QR staging fits");
 
 LQ_DEV double block_max(double v, double *red) {

@@ -52,8 +52,9 @@ template <int NB> constexpr int qr_rpt() { return NB > 256 ? 2 : 1; }  // panel 
 // v_q^T a_j = base_j + s x^T a_j, where base_j is the pivot-row entry (R(q, j)
 // for TS, A(pivot, j) for GEQRT), and the same form gives the Gram entries
 // v_j^T v_q that extend the compact-WY factor T.  The reduction of column q+1
-// is formed right after column q's update, so each column costs one barrier
-// (partial sums ping-pong between two LDS buffers).
+// is formed right after column q's update (partial sums ping-pong between two
+// LDS buffers); one wave turns the sums into the reflector, so each column
+// costs two barriers.
 // On return Ys holds V (explicit zeros/ones for GEQRT) and Ts holds T.
 // ---------------------------------------------------------------------------
 // A block reflector V (nb x IB) staged in LDS is kept twice: column-major
@@ -72,9 +73,20 @@ template <int NB, class S> LQ_DEV void put_v(S *Ys, int r, int q, S v) {
 }
 
 struct PanelLds {
-    double red[2][IB * 4];  // [buffer][j][wave], FP64 partial sums
+    double red[2][IB * 4];  // [buffer][j][wave]: the waves' partial sums (values of type S)
     double prow[2][IB];     // GEQRT: pivot row of the column being reduced (type S)
+    double pmax[4];         // per-wave largest magnitude of the panel block
+    double dcol[IB];        // column q: d_j = v_q^T a_j (j > q), v_j^T v_q (j < q) (type S)
+    double wcol[IB];        // column q: w_j = tau d_j, the rank-1 update's row (type S)
+    double sc[4];           // column q: scal, tau, beta (type S)
 };
+
+template <class S> LQ_DEV S rlane(S v, int lane) {
+    if constexpr (sizeof(S) == 4) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    else
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                                __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
 
 // Partial sums of column q's reduction into pl->red[q & 1]; for GEQRT the
 // owner of the pivot row also publishes it.
@@ -83,11 +95,11 @@ LQ_DEV void qr_reduce(S (&P)[qr_rpt<NB>()][IB], int c0, PanelLds *pl) {
     constexpr int RPT = qr_rpt<NB>();
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
     const int pr = c0 + Q;
-    double x[RPT];
+    S x[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int r = tid + 256 * u;
-        x[u] = (TS ? r < NB : (r > pr && r < NB)) ? (double)P[u][Q] : 0.0;
+        x[u] = (TS ? r < NB : (r > pr && r < NB)) ? P[u][Q] : (S)0;
         if (!TS && r == pr) {
 #pragma unroll
             for (int j = 0; j < IB; ++j) ((S *)pl->prow[Q & 1])[j] = P[u][j];
@@ -95,87 +107,94 @@ LQ_DEV void qr_reduce(S (&P)[qr_rpt<NB>()][IB], int c0, PanelLds *pl) {
     }
 #pragma unroll
     for (int half = 0; half < IB / 16; ++half) {
-        double part[16];
+        S part[16];
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
             const int j = 16 * half + jj;
-            double acc = 0;
+            S acc = 0;
 #pragma unroll
-            for (int u = 0; u < RPT; ++u) acc += x[u] * (double)P[u][j];
+            for (int u = 0; u < RPT; ++u) acc += x[u] * P[u][j];
             part[jj] = acc;
         }
-        const double tot = xreduce16<double>(part);
-        if ((l & 3) == 0) pl->red[Q & 1][(16 * half + (l >> 2)) * 4 + w] = tot;
+        const S tot = xreduce16<S>(part);
+        if ((l & 3) == 0) ((S *)pl->red[Q & 1])[(16 * half + (l >> 2)) * 4 + w] = tot;
     }
 }
 
-// TS: R's row q is read by every thread during column q, so its new values
-// (and beta on the diagonal) are written one barrier later: `pend` carries
-// this thread's write (index into Rb, -1 for none) into the next column.
+// Column q of the panel, between two barriers.  Wave 0 turns the reduced sums
+// into the reflector: lane j (j < IB) forms f_j = x^T a_j from the four waves'
+// partials and the pivot-row entry base_j (row q of R's row-major block for
+// TS), every lane takes f_q and base_q from lane q for the norm, and lane j
+// forms d_j and w_j = tau d_j and, for TS, writes R(q, j) at once (no other
+// wave reads R's row q).  A barrier then hands scal, tau, beta, d and w to
+// every thread for the rank-1 update of its rows and the new column of T.
+// The products and lane sums are in the storage precision on a panel block
+// scaled to a largest magnitude near 1 (panel_qr), so they neither overflow
+// nor underflow; a column whose remaining norm is below 2^-50 (FP32) or
+// 2^-500 (FP64) of that is left as it is (tau = 0), as for an exactly zero
+// one.
 template <int NB, class S, bool TS, int Q>
-LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *pl, int &pend_i, S &pend_v) {
+LQ_DEV void qr_column(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds *pl) {
     constexpr int RPT = qr_rpt<NB>();
-    const int tid = threadIdx.x;
+    constexpr S TINY = sizeof(S) == 4 ? (S)0x1.0p-100 : (S)0x1.0p-1000;  // of the squared norm
+    const int tid = threadIdx.x, l = lane_id();
     const int pr = c0 + Q;  // GEQRT pivot row
-    if (TS && pend_i >= 0) Rb[pend_i] = pend_v;
-    // The sums, the norm and the reflector scalars are FP64 whatever S is: for
-    // 4-byte storage the squares and products of FP32 values can neither
-    // overflow nor underflow in FP64, so no scaling of the column is needed
-    // (the FP32 sums would lose a tail below ~1e-19 and overflow above ~1e19).
-    // f(j) = x^T a_j (the four waves' partials of column j are adjacent);
-    // base(j) = the pivot-row entry (row q of R's row-major block for TS).
-    // Both are re-read from LDS where needed rather than held in registers.
-    const double *red = pl->red[Q & 1];
-    auto f = [&](int j) { return (red[j * 4] + red[j * 4 + 1]) + (red[j * 4 + 2] + red[j * 4 + 3]); };
-    auto base = [&](int j) -> double {
-        if (TS) return j >= Q ? (double)Rb[Q * IB + j] : 0.0;
-        return (double)((const S *)pl->prow[Q & 1])[j];
-    };
-    const double ss = f(Q), alpha = base(Q);
-    double tau = 0, beta = alpha, scal = 1;
-    if (ss != 0.0) {
-        const double nrm = sqrt(alpha * alpha + ss);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
+    S *dcol = (S *)pl->dcol, *wcol = (S *)pl->wcol, *sc = (S *)pl->sc;
+    if (tid < 64) {
+        const int j = l & (IB - 1);
+        const S *red = (const S *)pl->red[Q & 1];
+        const S fj = (red[j * 4] + red[j * 4 + 1]) + (red[j * 4 + 2] + red[j * 4 + 3]);
+        const S bj = TS ? (j >= Q ? Rb[Q * IB + j] : (S)0) : ((const S *)pl->prow[Q & 1])[j];
+        const S ss = rlane(fj, Q), alpha = rlane(bj, Q);
+        S tau = 0, beta = alpha, scal = 1;
+        if (ss >= TINY) {
+            const S nrm = sqrt(alpha * alpha + ss);
+            beta = alpha >= (S)0 ? -nrm : nrm;
+            const S g = alpha - beta;  // |g| >= nrm
+            scal = (S)1 / g;
+            tau = -g / beta;
+        }
+        const S dj = j == Q ? (S)0 : bj + scal * fj;
+        const S wj = j > Q ? tau * dj : (S)0;
+        if (l < IB) {
+            dcol[j] = dj;
+            wcol[j] = wj;
+            if (TS && j >= Q) Rb[Q * IB + j] = j == Q ? beta : bj - wj;
+        }
+        if (l == 0) { sc[0] = scal; sc[1] = tau; sc[2] = beta; }
     }
-    double d[IB];  // v_q^T a_j (j > q) and v_j^T v_q (j < q)
-#pragma unroll
-    for (int j = 0; j < IB; ++j) d[j] = j == Q ? 0.0 : base(j) + scal * f(j);
+    __syncthreads();
+    const S scal = sc[0], tau = sc[1];
     S vq[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int r = tid + 256 * u;
         const bool tail = TS ? r < NB : (r > pr && r < NB);
-        vq[u] = tail ? (S)((double)P[u][Q] * scal) : ((!TS && r == pr) ? (S)1 : (S)0);
+        vq[u] = tail ? P[u][Q] * scal : ((!TS && r == pr) ? (S)1 : (S)0);
         if (tail) P[u][Q] = vq[u];
-        if (!TS && r == pr) P[u][Q] = (S)beta;
+        if (!TS && r == pr) P[u][Q] = sc[2];
     }
-    pend_i = -1;
-    if (TS && tid == 0) { pend_i = Q * IB + Q; pend_v = (S)beta; }
-    if (tau != 0.0) {
+    if (tau != (S)0) {
 #pragma unroll
         for (int j = Q + 1; j < IB; ++j) {
-            const double wd = tau * d[j];
-            const S wj = (S)wd;
+            const S wj = wcol[j];
 #pragma unroll
             for (int u = 0; u < RPT; ++u) P[u][j] -= vq[u] * wj;
-            if (TS && tid == j) { pend_i = Q * IB + j; pend_v = (S)(base(j) - wd); }
         }
     }
-    // T(0:q, q) = -tau T(0:q, 0:q) G(0:q, q), with G(p, q) = v_p^T v_q = d[p]
+    // T(0:q, q) = -tau T(0:q, 0:q) G(0:q, q), with G(p, q) = v_p^T v_q = d_p;
+    // the strictly lower part of T is stored as zeros
     if (tid < Q) {
-        double acc = 0;
+        S acc = 0;
 #pragma unroll
-        for (int p = 0; p < Q; ++p)
-            if (p >= tid) acc += (double)Ts[p * IB + tid] * d[p];
-        Ts[Q * IB + tid] = (S)(-tau * acc);
+        for (int p = 0; p < Q; ++p) acc += Ts[p * IB + tid] * dcol[p];
+        Ts[Q * IB + tid] = -tau * acc;
     } else if (tid < IB) {
-        Ts[Q * IB + tid] = tid == Q ? (S)tau : (S)0;
+        Ts[Q * IB + tid] = tid == Q ? tau : (S)0;
     }
     if constexpr (Q + 1 < IB) {
         qr_reduce<NB, S, TS, Q + 1>(P, c0, pl);
-        __syncthreads();  // column q+1's sums, its pivot row and R's row q+1 are visible
+        __syncthreads();  // column q+1's sums and pivot row, R's row q+1, T's column q are visible
     }
 }
 
@@ -184,28 +203,61 @@ LQ_DEV void qr_columns(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds 
                        std::integer_sequence<int, Qs...>) {
     qr_reduce<NB, S, TS, 0>(P, c0, pl);
     __syncthreads();
-    int pend_i = -1;
-    S pend_v = 0;
-    (qr_column<NB, S, TS, Qs>(P, c0, Rb, Ts, pl, pend_i, pend_v), ...);
-    if (TS) {
-        __syncthreads();  // every read of R's last row is done
-        if (pend_i >= 0) Rb[pend_i] = pend_v;
-    }
+    (qr_column<NB, S, TS, Qs>(P, c0, Rb, Ts, pl), ...);
 }
 
+// Power-of-two scaling: the block (and, for TS, R's diagonal block) is
+// multiplied by 2^-e, e the exponent of its largest magnitude, before the
+// columns are reduced, and the R entries it produces are multiplied back by
+// 2^e.  Multiplying by a power of two is exact, and the reflectors V, T and
+// tau do not depend on the scale, so the result equals the unscaled
+// computation wherever that one neither overflows nor underflows; products
+// of entries of a block near 1 in magnitude cannot overflow, and only
+// entries 2^-60 below the block's largest one can underflow, which is far
+// below the storage rounding of the block (Householder QR is normwise
+// backward stable).
 template <int NB, class S, bool TS>
 LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
     constexpr int RPT = qr_rpt<NB>();
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, l = lane_id(), w = wave_id();
     S P[RPT][IB];
+    double mx = 0.0;
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int r = tid + 256 * u;
 #pragma unroll
-        for (int q = 0; q < IB; ++q)
+        for (int q = 0; q < IB; ++q) {
             P[u][q] = (r < NB && (TS || r >= c0)) ? A[r + (c0 + q) * NB] : (S)0;
+            mx = fmax(mx, fabs((double)P[u][q]));
+        }
     }
+    static_assert(IB * IB == WG, "R's diagonal block has one entry per thread");
+    if (TS) mx = fmax(mx, fabs((double)Rb[tid]));
+    mx = wave_max(mx);
+    if (l == 0) pl->pmax[w] = mx;
+    __syncthreads();
+    mx = fmax(fmax(pl->pmax[0], pl->pmax[1]), fmax(pl->pmax[2], pl->pmax[3]));
+    const int e = (mx > 0.0 && mx <= 1.7976931348623157e308) ? ilogb(mx) : 0;
+    const int ec = e < -120 ? -120 : (e > 120 ? 120 : e);
+    const S down = (S)ldexp(1.0, -ec), up = (S)ldexp(1.0, ec);
+#pragma unroll
+    for (int u = 0; u < RPT; ++u)
+#pragma unroll
+        for (int q = 0; q < IB; ++q) P[u][q] *= down;
+    if (TS) Rb[tid] *= down;  // read by other threads only after the first barrier of qr_columns
     qr_columns<NB, S, TS>(P, c0, Rb, Ts, pl, std::make_integer_sequence<int, IB>{});
+    if (TS) {
+        __syncthreads();  // every column's writes of R are in place
+        Rb[tid] *= up;
+    } else {
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int r = tid + 256 * u;
+#pragma unroll
+            for (int q = 0; q < IB; ++q)
+                if (r >= c0 && r <= c0 + q) P[u][q] *= up;  // R's rows of this block (beta on the diagonal)
+        }
+    }
     // write the panel back and expose V to the trailing update
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
