@@ -113,13 +113,16 @@ static double tile_maxabs(const double *A, int64_t lda, int64_t rows, int64_t co
 /* that is exactly zero is skipped (no interchange, no scaling) and         */
 /* reported.  Returns the 1-based index of the first zero pivot, 0 if none. */
 /* ---------------------------------------------------------------------- */
-int64_t oracle_gepp(int64_t m, double *W, int64_t ldw, int32_t *ipiv)
+/* The same elimination on a tall rows x cols block (rows >= cols): the     */
+/* pivot of column c is searched over rows c..rows-1 (the diagonal domain   */
+/* of Sec. 2.1 stacks several tiles of the panel).                          */
+static int64_t gepp_rect(int64_t rows, int64_t cols, double *W, int64_t ldw, int32_t *ipiv)
 {
     int64_t first_zero = 0;
-    for (int64_t c = 0; c < m; ++c) {
+    for (int64_t c = 0; c < cols; ++c) {
         int64_t p = c;
         double best = fabs(W[IX(c, c, ldw)]);
-        for (int64_t r = c + 1; r < m; ++r) {
+        for (int64_t r = c + 1; r < rows; ++r) {
             double a = fabs(W[IX(r, c, ldw)]);
             if (a > best) { best = a; p = r; }
         }
@@ -129,19 +132,61 @@ int64_t oracle_gepp(int64_t m, double *W, int64_t ldw, int32_t *ipiv)
             continue;
         }
         if (p != c)
-            for (int64_t j = 0; j < m; ++j) {
+            for (int64_t j = 0; j < cols; ++j) {
                 double t = W[IX(c, j, ldw)];
                 W[IX(c, j, ldw)] = W[IX(p, j, ldw)];
                 W[IX(p, j, ldw)] = t;
             }
         double piv = W[IX(c, c, ldw)];
-        for (int64_t r = c + 1; r < m; ++r) W[IX(r, c, ldw)] /= piv;
-        for (int64_t j = c + 1; j < m; ++j) {
+        for (int64_t r = c + 1; r < rows; ++r) W[IX(r, c, ldw)] /= piv;
+        for (int64_t j = c + 1; j < cols; ++j) {
             double u = W[IX(c, j, ldw)];
-            for (int64_t r = c + 1; r < m; ++r) W[IX(r, j, ldw)] -= W[IX(r, c, ldw)] * u;
+            for (int64_t r = c + 1; r < rows; ++r) W[IX(r, j, ldw)] -= W[IX(r, c, ldw)] * u;
         }
     }
     return first_zero;
+}
+
+int64_t oracle_gepp(int64_t m, double *W, int64_t ldw, int32_t *ipiv)
+{
+    return gepp_rect(m, m, W, ldw, ipiv);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Diagonal domain of step k (Sec. 2.1, last paragraph; Sec. 3.1 and 3.3):  */
+/* the panel tiles held by the node that holds A_kk when tile rows are      */
+/* dealt cyclically over p rows of nodes, i.e. the tiles i >= k with        */
+/* i = k (mod p), in increasing order (tiles[0] = k).  p = 0: the diagonal  */
+/* tile alone.  The domain's tiles are stacked in that order; stacked row s */
+/* is row s % nb of tile tiles[s / nb] (only the last tile of the matrix   */
+/* can be short, and it comes last).                                        */
+/* ---------------------------------------------------------------------- */
+static int64_t domain_tiles(int64_t k, int64_t n, int64_t p, int64_t *tiles)
+{
+    int64_t d = 0;
+    tiles[d++] = k;
+    if (p > 0)
+        for (int64_t i = k + p; i < n; i += p) tiles[d++] = i;
+    return d;
+}
+
+static int64_t domain_row(int64_t s, const int64_t *tiles, int64_t nb)
+{
+    return tiles[s / nb] * nb + s % nb;
+}
+
+/* Row interchanges of a domain factorization, in order, on columns c0..c1-1
+ * of the N x * matrix X: stacked row c <-> stacked row dpiv[c]. */
+static void domain_swap(int64_t mk, const int32_t *dpiv, const int64_t *tiles, int64_t nb,
+                        double *X, int64_t ldx, int64_t c0, int64_t c1)
+{
+    for (int64_t c = 0; c < mk; ++c) {
+        if (dpiv[c] == c) continue;
+        int64_t a = domain_row(c, tiles, nb), b = domain_row(dpiv[c], tiles, nb);
+        for (int64_t j = c0; j < c1; ++j) {
+            double t = X[IX(a, j, ldx)]; X[IX(a, j, ldx)] = X[IX(b, j, ldx)]; X[IX(b, j, ldx)] = t;
+        }
+    }
 }
 
 /* ||W^{-1}||_1 from the factors P W = L U: column j of W^{-1} solves
@@ -369,11 +414,19 @@ static double step_units(int64_t r, int is_qr)
 /*                    the forward-transformed right-hand sides.            */
 /* Outputs ipiv, Tq, dec, s, m, margin may each be NULL.                   */
 /* ---------------------------------------------------------------------- */
-int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
-                  uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
-                  double *B, int64_t ldb, int64_t nrhs,
-                  int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
-                  double *margin_out, double *diag)
+/*   domain_stride    p of the diagonal domain (see domain_tiles); 0: the  */
+/*                    diagonal tile alone.  With a domain of more than one  */
+/*                    tile the LU attempt is GEPP on the stacked domain,    */
+/*                    the criterion sees A_kk and the sub-diagonal tiles    */
+/*                    after its interchanges (Sec. 3.1), an LU step applies */
+/*                    them to the trailing columns of the domain's rows and */
+/*                    stores the domain's multipliers, and ipiv[k*nb + c]   */
+/*                    holds the stacked row exchanged at column c.          */
+int oracle_factor_domain(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
+                         uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
+                         double *B, int64_t ldb, int64_t nrhs,
+                         int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
+                         double *margin_out, double *diag, int32_t domain_stride)
 {
     if (N < 1) return -1;
     if (nb < 1) return -4;
@@ -382,6 +435,7 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
     if (criterion < 0 || criterion > 4) return -5;
     if (criterion == CRIT_FORCED && !forced) return -8;
     if (B && ldb < N) return -12;
+    if (domain_stride < 0) return -21;
 
     const int64_t n = (N + nb - 1) / nb;
     if (nsteps < 0 || nsteps > n) nsteps = n;
@@ -394,6 +448,10 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
     double *lmax = (double *)malloc((size_t)nb * sizeof(double));
     double *nrm_before = diag ? (double *)malloc((size_t)n * (size_t)n * sizeof(double)) : NULL;
     (void)colsum_scratch;
+    int64_t *dtile = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    double *Wd = domain_stride > 0 ? (double *)malloc((size_t)N * (size_t)nb * sizeof(double)) : NULL;
+    double *Pd = domain_stride > 0 ? (double *)malloc((size_t)N * (size_t)nb * sizeof(double)) : NULL;
+    int32_t *dpiv = (int32_t *)calloc((size_t)nb, sizeof(int32_t));
 
     if (diag) {
         for (int q = 0; q < DG_COUNT; ++q) diag[q] = 0.0;
@@ -418,6 +476,10 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
             if (k == 0) { max_tile0 = max_tile; max_elem0 = max_elem; }
         }
 
+        const int64_t d = domain_tiles(k, n, domain_stride, dtile);
+        const int64_t R = (d - 1) * nb + tsize(N, nb, dtile[d - 1]);  /* rows of the stacked domain */
+        int64_t zero_piv;
+        if (d == 1) {
         /* ---- Factor: backup copy W of A_kk, GEPP on the copy (Sec. 4, Backup Panel / LU On Panel) */
         for (int64_t j = 0; j < mk; ++j)
             for (int64_t i = 0; i < mk; ++i) W[IX(i, j, nb)] = Akk[IX(i, j, lda)];
@@ -426,7 +488,31 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
             for (int64_t i = 0; i < mk; ++i) { double a = fabs(Akk[IX(i, j, lda)]); if (a > b) b = a; }
             lmax[j] = b;
         }
-        int64_t zero_piv = oracle_gepp(mk, W, nb, piv);
+        zero_piv = oracle_gepp(mk, W, nb, piv);
+        } else {
+            /* ---- Factor on the diagonal domain: GEPP on a copy of the stacked
+             * domain tiles; W receives its top block L11\U (the diagonal tile
+             * after the domain's interchanges, Sec. 3.1), whose own pivots are
+             * then the identity. */
+            for (int64_t j = 0; j < mk; ++j)
+                for (int64_t r = 0; r < R; ++r) Wd[IX(r, j, R)] = A[IX(domain_row(r, dtile, nb), k * nb + j, lda)];
+            memcpy(Pd, Wd, (size_t)R * (size_t)mk * sizeof(double));
+            for (int64_t j = 0; j < mk; ++j) { /* MUMPS: local column maxima over the domain */
+                double b = 0.0;
+                for (int64_t r = 0; r < R; ++r) { double a = fabs(Wd[IX(r, j, R)]); if (a > b) b = a; }
+                lmax[j] = b;
+            }
+            zero_piv = gepp_rect(R, mk, Wd, R, dpiv);
+            for (int64_t j = 0; j < mk; ++j)
+                for (int64_t i = 0; i < mk; ++i) W[IX(i, j, nb)] = Wd[IX(i, j, R)];
+            for (int64_t c = 0; c < mk; ++c) piv[c] = (int32_t)c;
+            /* the original panel values of the domain, permuted like the rows of Wd */
+            for (int64_t c = 0; c < mk; ++c)
+                if (dpiv[c] != c)
+                    for (int64_t j = 0; j < mk; ++j) {
+                        double t = Pd[IX(c, j, R)]; Pd[IX(c, j, R)] = Pd[IX(dpiv[c], j, R)]; Pd[IX(dpiv[c], j, R)] = t;
+                    }
+        }
 
         /* ---- Check: criterion inputs (Sec. 3) */
         double s = 0.0, m = 0.0;
@@ -436,12 +522,15 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
             s = 1.0 / inv;
         }
         for (int64_t j = 0; j < mk; ++j) away[j] = 0.0;
-        for (int64_t i = k + 1; i < n; ++i) {
+        for (int64_t i = k + 1, t_dom = 1; i < n; ++i) {
             const double *Aik = &A[IX(i * nb, k * nb, lda)];
             int64_t mi = tsize(N, nb, i);
-            double t = oracle_tile_norm1(Aik, lda, mi, mk);
+            const int in_domain = t_dom < d && dtile[t_dom] == i;
+            double t = in_domain ? oracle_tile_norm1(&Pd[IX(t_dom * nb, 0, R)], R, mi, mk)
+                                 : oracle_tile_norm1(Aik, lda, mi, mk);
             if (criterion == CRIT_SUM) m += t;
             else if (t > m || isnan(t)) m = t;
+            if (in_domain) { ++t_dom; continue; } /* MUMPS: away_max is over the tiles off the domain */
             for (int64_t j = 0; j < mk; ++j)
                 for (int64_t r = 0; r < mi; ++r) {
                     double a = fabs(Aik[IX(r, j, lda)]);
@@ -513,12 +602,25 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
             if (zero_piv && diag && diag[DG_INFO] == 0.0) diag[DG_INFO] = (double)(k * nb + zero_piv);
             for (int64_t j = 0; j < mk; ++j)
                 for (int64_t i = 0; i < mk; ++i) Akk[IX(i, j, lda)] = W[IX(i, j, nb)];
-            if (ipiv) for (int64_t c = 0; c < mk; ++c) ipiv[k * nb + c] = piv[c];
+            if (ipiv) for (int64_t c = 0; c < mk; ++c) ipiv[k * nb + c] = d == 1 ? piv[c] : dpiv[c];
+            if (d > 1) {
+                /* the domain's interchanges on the trailing columns of its rows
+                 * (and on B), and its multipliers below the diagonal tile; the
+                 * diagonal tile then needs no further pivoting (piv = identity) */
+                domain_swap(mk, dpiv, dtile, nb, A, lda, (k + 1) * nb, N);
+                if (B) domain_swap(mk, dpiv, dtile, nb, B, ldb, 0, nrhs);
+                for (int64_t t = 1; t < d; ++t)
+                    for (int64_t j = 0; j < mk; ++j)
+                        for (int64_t r = 0; r < tsize(N, nb, dtile[t]); ++r)
+                            A[IX(dtile[t] * nb + r, k * nb + j, lda)] = Wd[IX(t * nb + r, j, R)];
+            }
 #pragma omp parallel for schedule(dynamic, 1)
             for (int64_t t = 0; t < 2 * (n - k - 1); ++t) {
-                if (t < n - k - 1) { /* Eliminate A_ik */
+                if (t < n - k - 1) { /* Eliminate A_ik (done by the domain factorization for its tiles) */
                     int64_t i = k + 1 + t;
-                    trsm_right_upper(mk, W, nb, tsize(N, nb, i), &A[IX(i * nb, k * nb, lda)], lda);
+                    int in_domain = 0;
+                    for (int64_t q = 1; q < d; ++q) in_domain |= dtile[q] == i;
+                    if (!in_domain) trsm_right_upper(mk, W, nb, tsize(N, nb, i), &A[IX(i * nb, k * nb, lda)], lda);
                 } else { /* Apply A_kj */
                     int64_t j = k + 1 + (t - (n - k - 1));
                     swptrsm(mk, W, nb, piv, tsize(N, nb, j), &A[IX(k * nb, j * nb, lda)], lda);
@@ -585,7 +687,18 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
         diag[DG_GROWTH_ELEM] = max_elem0 > 0 ? max_elem / max_elem0 : 0.0;
     }
     free(piv); free(W); free(Tloc); free(colsum_scratch); free(away); free(lmax); free(nrm_before);
+    free(dtile); free(Wd); free(Pd); free(dpiv);
     return 0;
+}
+
+int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
+                  uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
+                  double *B, int64_t ldb, int64_t nrhs,
+                  int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
+                  double *margin_out, double *diag)
+{
+    return oracle_factor_domain(N, A, lda, nb, criterion, alpha, seed, forced, mumps_reading, nsteps, B, ldb, nrhs,
+                                ipiv, Tq, dec, s_out, m_out, margin_out, diag, 0);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -593,15 +706,27 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
 /* then block back-substitution with the upper-triangular factor.  F, ipiv, */
 /* Tq, dec are oracle_factor outputs of a full factorization.              */
 /* ---------------------------------------------------------------------- */
-void oracle_forward(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
-                    const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs)
+void oracle_forward_domain(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+                           const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
+                           int32_t domain_stride)
 {
     const int64_t n = (N + nb - 1) / nb;
+    int64_t *dtile = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int32_t *ident = (int32_t *)malloc((size_t)nb * sizeof(int32_t));
+    for (int64_t c = 0; c < nb; ++c) ident[c] = (int32_t)c;
     for (int64_t k = 0; k < n; ++k) {
         const int64_t mk = tsize(N, nb, k);
         const double *Fkk = &F[IX(k * nb, k * nb, ldf)];
         double *Bk = &B[IX(k * nb, 0, ldb)];
-        if (dec[k]) {
+        const int64_t d = domain_tiles(k, n, domain_stride, dtile);
+        if (dec[k] && d > 1) {
+            domain_swap(mk, &ipiv[k * nb], dtile, nb, B, ldb, 0, nrhs);
+            swptrsm(mk, Fkk, ldf, ident, nrhs, Bk, ldb);
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t i = k + 1; i < n; ++i)
+                gemm_minus(tsize(N, nb, i), nrhs, mk, &F[IX(i * nb, k * nb, ldf)], ldf, Bk, ldb,
+                           &B[IX(i * nb, 0, ldb)], ldb);
+        } else if (dec[k]) {
             swptrsm(mk, Fkk, ldf, &ipiv[k * nb], nrhs, Bk, ldb);
 #pragma omp parallel for schedule(dynamic, 1)
             for (int64_t i = k + 1; i < n; ++i)
@@ -614,6 +739,13 @@ void oracle_forward(int64_t N, const double *F, int64_t ldf, int64_t nb, const i
                              &Tq[((size_t)k * n + i) * nb * nb], nb, nrhs, Bk, ldb, &B[IX(i * nb, 0, ldb)], ldb);
         }
     }
+    free(dtile); free(ident);
+}
+
+void oracle_forward(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+                    const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs)
+{
+    oracle_forward_domain(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs, 0);
 }
 
 void oracle_backward(int64_t N, const double *F, int64_t ldf, int64_t nb, double *B, int64_t ldb, int64_t nrhs)
@@ -638,6 +770,14 @@ void oracle_solve(int64_t N, const double *F, int64_t ldf, int64_t nb, const int
                   const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs)
 {
     oracle_forward(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs);
+    oracle_backward(N, F, ldf, nb, B, ldb, nrhs);
+}
+
+void oracle_solve_domain(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+                         const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
+                         int32_t domain_stride)
+{
+    oracle_forward_domain(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs, domain_stride);
     oracle_backward(N, F, ldf, nb, B, ldb, nrhs);
 }
 

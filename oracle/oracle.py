@@ -55,10 +55,17 @@ def lib():
         L.oracle_factor.restype = C.c_int
         L.oracle_factor.argtypes = [i64, dp, i64, i64, i32, f64, C.c_uint64, bp, i32, i64,
                                     dp, i64, i64, ip, dp, bp, dp, dp, dp, dp]
+        L.oracle_factor_domain.restype = C.c_int
+        L.oracle_factor_domain.argtypes = [i64, dp, i64, i64, i32, f64, C.c_uint64, bp, i32, i64,
+                                           dp, i64, i64, ip, dp, bp, dp, dp, dp, dp, i32]
         L.oracle_solve.restype = None
         L.oracle_solve.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64]
+        L.oracle_solve_domain.restype = None
+        L.oracle_solve_domain.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64, i32]
         L.oracle_forward.restype = None
         L.oracle_forward.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64]
+        L.oracle_forward_domain.restype = None
+        L.oracle_forward_domain.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64, i32]
         L.oracle_backward.restype = None
         L.oracle_backward.argtypes = [i64, dp, i64, i64, dp, i64, i64]
         L.oracle_gepp.restype = i64
@@ -116,6 +123,7 @@ class OracleFactors:
     margin: np.ndarray
     diag: np.ndarray         # see DG_*
     Bt: np.ndarray | None = None   # forward-transformed B in augmented mode
+    domain: int = 0          # stride p of the diagonal domain (0: the diagonal tile alone)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -127,8 +135,10 @@ class OracleFactors:
 
 
 def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading=0,
-           nsteps=-1, B=None) -> OracleFactors:
-    """Hybrid LU-QR factorization (Alg. 1) of a copy of A."""
+           nsteps=-1, B=None, domain=0) -> OracleFactors:
+    """Hybrid LU-QR factorization (Alg. 1) of a copy of A.  domain = p > 0
+    pivots the LU attempt over the diagonal domain (the panel tiles k, k+p,
+    k+2p, ...; Sec. 2.1), domain = 0 within the diagonal tile."""
     A = _fortran(A)
     N = A.shape[0]
     assert A.shape == (N, N)
@@ -150,12 +160,17 @@ def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading
     if B is not None:
         Bt = _fortran(B.reshape(N, -1) if B.ndim == 1 else B)
         nrhs = Bt.shape[1]
-    rc = lib().oracle_factor(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
-                             int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
-                             _b(dec), _d(s), _d(m), _d(margin), _d(diag))
+    if domain:
+        rc = lib().oracle_factor_domain(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
+                                        int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
+                                        _b(dec), _d(s), _d(m), _d(margin), _d(diag), int(domain))
+    else:
+        rc = lib().oracle_factor(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
+                                 int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
+                                 _b(dec), _d(s), _d(m), _d(margin), _d(diag))
     if rc != 0:
         raise ValueError(f"oracle_factor rejected argument {-rc}")
-    return OracleFactors(N, nb, A, ipiv, Tq, dec, s, m, margin, diag, Bt)
+    return OracleFactors(N, nb, A, ipiv, Tq, dec, s, m, margin, diag, Bt, int(domain))
 
 
 def solve(fac: OracleFactors, B):
@@ -163,15 +178,19 @@ def solve(fac: OracleFactors, B):
     B = np.asarray(B, dtype=np.float64)
     vec = B.ndim == 1
     X = _fortran(B.reshape(fac.N, -1))
-    lib().oracle_solve(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
-                       _d(X), fac.N, X.shape[1])
+    if fac.domain:
+        lib().oracle_solve_domain(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
+                                  _d(X), fac.N, X.shape[1], fac.domain)
+    else:
+        lib().oracle_solve(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
+                           _d(X), fac.N, X.shape[1])
     return X[:, 0] if vec else X
 
 
 def forward(fac: OracleFactors, B):
     X = _fortran(np.asarray(B, dtype=np.float64).reshape(fac.N, -1))
-    lib().oracle_forward(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
-                         _d(X), fac.N, X.shape[1])
+    lib().oracle_forward_domain(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
+                                _d(X), fac.N, X.shape[1], fac.domain)
     return X
 
 
