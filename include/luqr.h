@@ -79,6 +79,18 @@ typedef struct {
                             and the full T factors) runs on a second stream of the
                             library's own, joined before step k+1's branch; nonzero: every
                             kernel in order on the caller's stream */
+    int32_t domain_stride; /* 0 (default): the LU attempt pivots within the diagonal tile.
+                            p > 0: within the diagonal domain (Sec. 2.1, last paragraph):
+                            the panel tiles k, k+p, k+2p, ... (the tiles a node holds when
+                            tile rows are dealt cyclically over p rows of nodes), stacked;
+                            the criterion then sees A_kk and the tiles below after the
+                            domain's interchanges (Sec. 3.1), MUMPS takes local_max over the
+                            domain and away_max off it (Sec. 3.3), and an LU step applies
+                            the interchanges to the trailing columns of the domain's rows.
+                            The pivots of such a step (luqr_export_factors) are stacked row
+                            indices.  Supported while the first step's domain has at most
+                            512 rows ((1 + (n-1)/p) nb <= 512), else LUQR_ERR_UNSUPPORTED;
+                            not by the batched entry points. */
 } luqr_opts;
 
 /* Device-side numerical status, read back by luqr_get_status. */

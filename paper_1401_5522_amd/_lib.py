@@ -29,7 +29,7 @@ class luqr_opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("criterion", C.c_int32), ("alpha", C.c_double),
                 ("precision", C.c_int32), ("nrhs_max", C.c_int32), ("seed", C.c_uint64),
                 ("forced", C.POINTER(C.c_int8)), ("nsteps", C.c_int32),
-                ("timing", C.c_int32), ("no_lookahead", C.c_int32)]
+                ("timing", C.c_int32), ("no_lookahead", C.c_int32), ("domain_stride", C.c_int32)]
 
 
 class luqr_status(C.Structure):
@@ -106,7 +106,7 @@ def lib() -> C.CDLL:
 
 
 def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed=0, forced=None,
-              nsteps=-1, timing=False, lookahead=True):
+              nsteps=-1, timing=False, lookahead=True, domain=0):
     o = luqr_opts()
     o.nb = int(nb)
     o.criterion = CRITERIA[criterion] if isinstance(criterion, str) else int(criterion)
@@ -121,6 +121,7 @@ def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed
     o.nsteps = int(nsteps)
     o.timing = 1 if timing else 0
     o.no_lookahead = 0 if lookahead else 1
+    o.domain_stride = int(domain)
     return o, keep
 
 

@@ -61,8 +61,12 @@ static int check_opts(int64_t N, const luqr_opts *o, int pos_opts) {
     if (o->criterion < 0 || o->criterion > 4) return -pos_opts;
     if (o->precision < 0 || o->precision > 2) return -pos_opts;
     if (o->criterion == LUQR_CRIT_FORCED && !o->forced) return -pos_opts;
+    if (o->domain_stride < 0) return -pos_opts;
     if (!pick_ops(o->nb, o->precision)) return LUQR_ERR_UNSUPPORTED;
-    (void)N;
+    if (o->domain_stride > 0) {  // the domain's GEPP holds at most 512 stacked rows in one workgroup
+        const int64_t n = (N + o->nb - 1) / o->nb;
+        if ((1 + (n - 1) / o->domain_stride) * (int64_t)o->nb > 512) return LUQR_ERR_UNSUPPORTED;
+    }
     return 0;
 }
 
@@ -70,7 +74,7 @@ extern "C" int64_t luqr_workspace_bytes(int64_t N, const luqr_opts *o) {
     if (N < 1) return -1;
     int rc = check_opts(N, o, 2);
     if (rc) return rc;
-    Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max);
+    Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride);
     return (int64_t)L.total;
 }
 
@@ -84,7 +88,7 @@ extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_
     if (rc) return rc;
     if (!dWork || ((uintptr_t)dWork & 255)) return -5;
     if (!out) return -8;
-    Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max);
+    Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride);
     if (work_bytes < (int64_t)L.total) return -6;
     luqr_factors_s *f = new (std::nothrow) luqr_factors_s;
     if (!f) return LUQR_ERR_HIP - (int)hipErrorOutOfMemory;
@@ -506,7 +510,7 @@ extern "C" int luqr_solve_noalloc(int64_t N, const double *dA, int64_t lda, cons
     if (!dX) return -8;
     if (ldx < N) return -9;
     if (max_iter < 0) return -10;
-    const Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max);
+    const Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride);
     if (o->nsteps >= 0 && o->nsteps < L.n) return -4;   // a partial factorization cannot be solved with
     if (L.total > (size_t)LUQR_NOALLOC_SCRATCH_BYTES || L.n > NOALLOC_MAX_STEPS) return LUQR_ERR_TOO_LARGE;
     void *base = nullptr;

@@ -236,6 +236,9 @@ struct DevStatus {
 struct Layout {
     int64_t N, n, nb, Np;
     int prec, nrhs_max;
+    int dstride;     // diagonal domain: tiles k, k+dstride, ... of the panel (0: the tile alone)
+    int64_t DR;      // rows of the largest stacked domain (nb without a domain)
+    size_t off_WD, off_dperm;
     int64_t sz_S;  // bytes of a storage element
     size_t off_At, off_Tf, off_gram, off_W, off_Linv, off_Dinv, off_ipiv, off_perm, off_zpiv;
     size_t off_dec, off_s, off_m, off_margin, off_status;
@@ -248,10 +251,12 @@ struct Layout {
 
 LQ_HD size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max) {
+inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max, int dstride = 0) {
     Layout L;
     L.N = N; L.nb = nb; L.n = (N + nb - 1) / nb; L.Np = L.n * nb;
     L.prec = prec; L.nrhs_max = nrhs_max < 1 ? 1 : nrhs_max;
+    L.dstride = dstride;
+    L.DR = (dstride > 0 ? 1 + (L.n - 1) / dstride : 1) * nb;
     L.sz_S = prec == P64 ? 8 : 4;
     const size_t n = L.n, b = nb, t2 = b * b;
     size_t o = 0;
@@ -276,6 +281,8 @@ inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max) {
     L.off_invpart = take((b / 16 + 1) * b * 8);
     L.off_flags = take(n * (b / IB) * 4 + 64);
     L.off_scale = take(n * n * 4);
+    L.off_WD = take(L.DR > (int64_t)b ? (size_t)L.DR * b * 8 : 8);
+    L.off_dperm = take(L.DR > (int64_t)b ? n * (size_t)L.DR * 4 : 8);
     const size_t Np = L.Np, r = L.nrhs_max;
     L.off_Y = take(Np * r * 8);
     L.off_Z = take(Np * r * 8);
@@ -318,8 +325,14 @@ struct Ctx {
     double *invpart; // partial column sums of |A_kk^{-1}| per 64-row block
     int *flags;      // QR-step pipeline: flag[i*(nb/IB) + b] = k+1 once block b of tile i's reflectors is published
     unsigned *tmax;  // per tile: bit pattern of max |a| (BF16 scaling), tile-major index (j*n+i)
+    double *WD;      // diagonal domain of the current step: stacked FP64 copy (DR x nb), factored
+    int *dperm;      // per step: stacked-row permutation of the domain, (P D)(s,:) = D(dperm[s],:)
     int64_t N, n;
     int nb;
+    int dstride, DR;
+    // tiles in the diagonal domain of step k, and whether tile row i > k is one of them
+    LQ_HD int dcount(int64_t k) const { return 1 + (dstride > 0 ? (int)((n - 1 - k) / dstride) : 0); }
+    LQ_HD bool indom(int64_t k, int64_t i) const { return dstride > 0 && i > k && (i - k) % dstride == 0; }
     LQ_HD int64_t toff(int64_t i, int64_t j) const { return (j * n + i) * (int64_t)nb * nb; }
     // T factor of panel tile (i,k), i >= k: panels packed one after another
     LQ_HD int64_t tqoff(int64_t i, int64_t k) const { return (k * n - k * (k - 1) / 2 + (i - k)) * (int64_t)nb * nb; }
@@ -337,7 +350,9 @@ inline Ctx make_ctx(const Layout &L, void *base) {
     c.tnorm = (double *)(b + L.off_tnorm); c.away = (double *)(b + L.off_away);
     c.lmax = (double *)(b + L.off_lmax); c.invpart = (double *)(b + L.off_invpart);
     c.flags = (int *)(b + L.off_flags); c.tmax = (unsigned *)(b + L.off_scale);
+    c.WD = (double *)(b + L.off_WD); c.dperm = (int *)(b + L.off_dperm);
     c.N = L.N; c.n = L.n; c.nb = (int)L.nb;
+    c.dstride = L.dstride; c.DR = (int)L.DR;
     return c;
 }
 

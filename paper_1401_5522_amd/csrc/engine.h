@@ -65,6 +65,7 @@ struct Eng {
             k_panel_decide<NB><<<1, WG, 0, st>>>(c, k, a);
             if (ev) (void)hipEventRecord(ev[E * k + 1], st);
             if (side && k > 0) (void)hipStreamWaitEvent(st, side->eb, 0);  // step k-1's bulk work
+            if (c.dcount(k) > 1) k_domain_swap<NB, P><<<(unsigned)rest * (NB / DSW_CW), WG, 0, st>>>(c, k);
             k_lu_apply<NB, P><<<1 + 2 * rest * (NB / lu_rb<NB>()), WG, 0, st>>>(c, k);
             if (ev) (void)hipEventRecord(ev[E * k + 2], st);
             constexpr int PER = NB / upd_bt<NB>();
@@ -102,6 +103,7 @@ struct Eng {
         for (int k = 0; k < n; ++k) {
             const int rest = n - k - 1;
             if (hdec[k] == 1) {
+                if (c.dcount(k) > 1) k_fwd_dswap<NB><<<dim3(1, (unsigned)((s.nrhs + 15) / 16)), WG, 0, st>>>(c, s, k);
                 k_fwd_lu_a<NB><<<dim3(RPT, ch), WG, 0, st>>>(c, s, k);
                 if (rest > 0) k_fwd_lu_b<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
             } else {

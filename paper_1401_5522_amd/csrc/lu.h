@@ -51,6 +51,20 @@ __global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
     if (b < rest * per_tile) {  // Eliminate: rows [r0, r0+RB) of A_ik times U^{-1}
         const int i = k + 1 + b / per_tile, r0 = (b % per_tile) * RB;
         S *X = At + c.toff(i, k);
+        if (c.indom(k, i)) {  // a domain tile: its multipliers come from the domain's GEPP
+            const int t = (i - k) / c.dstride;
+            for (int e = threadIdx.x; e < RB * NB; e += WG) {
+                const int r = r0 + e % RB, cc = e / RB;
+                const S o = (S)c.WD[(size_t)t * NB + r + (size_t)cc * c.DR];
+                X[r + cc * NB] = o;
+                lmx = fmaxf(lmx, fabsf((float)o));
+            }
+            if constexpr (P == PB16) {
+                for (int o = 32; o > 0; o >>= 1) lmx = fmaxf(lmx, __shfl_xor(lmx, o, 64));
+                if (lane_id() == 0) atomicMax(&c.tmax[(size_t)k * c.n + i], __float_as_uint(lmx));
+            }
+            return;
+        }
         const double *Ui = c.Dinv + (size_t)k * NB * NB;
         typename Tr<P>::acc acc[RB / WM / 16][NB / WN / 16];
         acc_zero<P, RB, NB, WM, WN>(acc);
@@ -92,6 +106,44 @@ __global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
         }
     }
     (void)wmax;
+}
+
+// Diagonal domain, LU step: the trailing columns j > k of the domain's rows
+// take the stacked permutation of its GEPP, (P D)(s,:) = D(dperm[s],:), so
+// that Apply needs no interchanges of its own (in the domain variant of
+// Sec. 2.1 the Apply step is modified accordingly).  Grid: (n-k-1) tile
+// columns x NB/16 chunks of 16 columns; a workgroup gathers the domain rows
+// of its chunk into LDS and writes back the rows that move.  BF16 tile maxima:
+// rows only move among the domain's tiles of one column, so their largest
+// maximum bounds each of them afterwards.
+constexpr int DSW_CW = 16;  // columns per workgroup
+template <int NB, int P>
+__global__ __launch_bounds__(WG) void k_domain_swap(Ctx c, int k) {
+    if (c.dec[k] != 1) return;
+    const int d = c.dcount(k);
+    if (d < 2) return;
+    typedef typename Tr<P>::S S;
+    __shared__ S buf[512 * DSW_CW];
+    const int R = d * NB;
+    const int j = k + 1 + (int)blockIdx.x / (NB / DSW_CW), c0 = ((int)blockIdx.x % (NB / DSW_CW)) * DSW_CW;
+    const int *pm = c.dperm + (size_t)k * c.DR;
+    S *At = (S *)c.At;
+    auto at = [&](int sr, int cc) -> S * {
+        return At + c.toff(k + (int64_t)(sr / NB) * c.dstride, j) + sr % NB + (size_t)(c0 + cc) * NB;
+    };
+    for (int e = threadIdx.x; e < R * DSW_CW; e += WG) buf[e] = *at(e % R, e / R);
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * DSW_CW; e += WG) {
+        const int r = e % R, sr = pm[r];
+        if (sr != r) *at(r, e / R) = buf[sr + (e / R) * R];
+    }
+    if constexpr (P == PB16) {
+        if (threadIdx.x == 0 && c0 == 0) {
+            unsigned mx = 0;
+            for (int t = 0; t < d; ++t) mx = max(mx, c.tmax[(size_t)j * c.n + k + (int64_t)t * c.dstride]);
+            for (int t = 0; t < d; ++t) atomicMax(&c.tmax[(size_t)j * c.n + k + (int64_t)t * c.dstride], mx);
+        }
+    }
 }
 
 // Update: A_ij -= A_ik A_kj over the (n-k-1)^2 trailing tiles, BT x BT

@@ -48,9 +48,8 @@ struct GetrfLds {
     double rowA[32], rowB[32];
 };
 
-template <int NB, int Q>
-LQ_DEV void lu_column(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g) {
-    constexpr int RPT = lu_rpt<NB>();
+template <int RPT, int Q>
+LQ_DEV void lu_column(double (&P)[RPT][32], int p0, int R, GetrfLds *g) {
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
     const int col = p0 + Q;
     double v = -1.0;
@@ -58,7 +57,7 @@ LQ_DEV void lu_column(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {  // rows ascending within the thread
         const int r = tid + 256 * u;
-        if (r >= col && r < NB) {
+        if (r >= col && r < R) {
             const double a = fabs(P[u][Q]);
             if (a > v) { v = a; idx = r; }
         }
@@ -111,7 +110,7 @@ LQ_DEV void lu_column(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g) {
 #pragma unroll
                 for (int j = 0; j < 32; ++j) P[u][j] = g->rowA[j];
             }
-            if (r > col && r < NB) {
+            if (r > col && r < R) {
                 const double lr = P[u][Q] / pv;
                 P[u][Q] = lr;
 #pragma unroll
@@ -121,26 +120,55 @@ LQ_DEV void lu_column(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g) {
     }
 }
 
-template <int NB, int... Qs>
-LQ_DEV void lu_columns(double (&P)[lu_rpt<NB>()][32], int p0, GetrfLds *g, std::integer_sequence<int, Qs...>) {
-    (lu_column<NB, Qs>(P, p0, g), ...);
+template <int RPT, int... Qs>
+LQ_DEV void lu_columns(double (&P)[RPT][32], int p0, int R, GetrfLds *g, std::integer_sequence<int, Qs...>) {
+    (lu_column<RPT, Qs>(P, p0, R, g), ...);
 }
 
-template <int NB, class S>
-LQ_DEV void getrf_diag(const Ctx &c, int k) {
-    constexpr int RPT = lu_rpt<NB>();
-    constexpr int BUFN = NB <= 256 ? 32 * (NB + 1) + NB * 33 : 32 * 33;
-    __shared__ double buf[BUFN];           // L21 / U12 staging of the trailing update
-    __shared__ double L11[32 * 33];
-    __shared__ int src[NB];
-    __shared__ unsigned long long lmx[NB];
-    __shared__ GetrfLds g;
+// The same elimination runs on the diagonal tile alone (R = NB rows, W the
+// step's copy, ld NB) or on the stacked diagonal domain (R = d NB rows of the
+// tiles k, k+p, ..., W = c.WD, ld DR): the pivot of each column is searched
+// over all R rows.  RPT = rows per thread / 256 >= R / 256.
+template <int NB, int RPT> struct GetrfSmem {
+    static constexpr int BUFN = (NB <= 256 && RPT == 1) ? 32 * (NB + 1) + NB * 33 : 32 * 33;
+    double buf[BUFN];  // L21 / U12 staging of the trailing update
+    double L11[32 * 33];
+    int src[256 * RPT];
+    unsigned long long lmx[NB];
+    GetrfLds g;
+};
+
+template <int NB, class S, int RPT>
+LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
+    const bool dom = c.dcount(k) > 1;
+    const int R = dom ? c.dcount(k) * NB : NB;
+    const int ldw = dom ? c.DR : NB;
+    GetrfSmem<NB, RPT> &sm = *(GetrfSmem<NB, RPT> *)smem;
+    double *buf = sm.buf, *L11 = sm.L11;
+    int *src = sm.src;
+    unsigned long long *lmx = sm.lmx;
+    GetrfLds &g = sm.g;
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
-    double *W = c.W + (size_t)k * NB * NB;
+    double *W = dom ? c.WD : c.W + (size_t)k * NB * NB;
     const S *A = (const S *)c.At + c.toff(k, k);
     for (int e = tid; e < NB; e += WG) lmx[e] = 0ull;
     if (tid == 0) g.zp = 0;
     __syncthreads();
+    if (dom) {
+        // stacked copy of the domain's tiles and its column maxima (MUMPS
+        // local_max over the domain): wave w takes columns w, w+4, ...
+        for (int col = w; col < NB; col += 4) {
+            double m = 0.0;
+            for (int r = l; r < R; r += 64) {
+                const S *T = (const S *)c.At + c.toff(k + (int64_t)(r / NB) * c.dstride, k);
+                const double a = (double)T[r % NB + (size_t)col * NB];
+                W[r + (size_t)col * ldw] = a;
+                m = nmax(m, fabs(a));
+            }
+            m = wave_nmax(m);
+            if (l == 0) lmx[col] = (unsigned long long)__double_as_longlong(m);
+        }
+    } else {
     // copy A_kk -> W (FP64) and its column maxima (MUMPS local_max)
     for (int e0 = 0; e0 < NB * NB; e0 += 8 * WG) {
         double a[8];
@@ -163,6 +191,7 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
             }
         }
     }
+    }
     __syncthreads();
     for (int e = tid; e < NB; e += WG) c.lmax[e] = __longlong_as_double((long long)lmx[e]);
     for (int p0 = 0; p0 < NB; p0 += 32) {
@@ -171,15 +200,15 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
         for (int u = 0; u < RPT; ++u) {
             const int r = tid + 256 * u;
 #pragma unroll
-            for (int j = 0; j < 32; ++j) P[u][j] = (r >= p0 && r < NB) ? W[r + (p0 + j) * NB] : 0.0;
+            for (int j = 0; j < 32; ++j) P[u][j] = (r >= p0 && r < R) ? W[r + (size_t)(p0 + j) * ldw] : 0.0;
         }
-        lu_columns<NB>(P, p0, &g, std::make_integer_sequence<int, 32>{});
+        lu_columns<RPT>(P, p0, R, &g, std::make_integer_sequence<int, 32>{});
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
             const int r = tid + 256 * u;
-            if (r >= p0 && r < NB) {
+            if (r >= p0 && r < R) {
 #pragma unroll
-                for (int j = 0; j < 32; ++j) W[r + (p0 + j) * NB] = P[u][j];
+                for (int j = 0; j < 32; ++j) W[r + (size_t)(p0 + j) * ldw] = P[u][j];
             }
             if (r >= p0 && r < p0 + 32) {
 #pragma unroll
@@ -188,8 +217,9 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
         }
         if (tid < 32) c.ipiv[(size_t)k * NB + p0 + tid] = g.piv[tid];
         // rows moved by the panel's interchanges: trow[t] receives row tsrc[t]
+        for (int r = p0 + tid; r < R; r += WG) src[r] = r;
+        __syncthreads();
         if (tid == 0) {
-            for (int r = p0; r < NB; ++r) src[r] = r;
             for (int q = 0; q < 32; ++q) {
                 const int a = p0 + q, b = g.piv[q];
                 const int t = src[a]; src[a] = src[b]; src[b] = t;
@@ -209,10 +239,10 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
                 if (cc >= p0 && cc < p0 + 32) continue;
                 double v[64];
 #pragma unroll
-                for (int t = 0; t < 64; ++t) v[t] = t < cnt ? W[g.tsrc[t] + cc * NB] : 0.0;
+                for (int t = 0; t < 64; ++t) v[t] = t < cnt ? W[g.tsrc[t] + (size_t)cc * ldw] : 0.0;
 #pragma unroll
                 for (int t = 0; t < 64; ++t)
-                    if (t < cnt) W[g.trow[t] + cc * NB] = v[t];
+                    if (t < cnt) W[g.trow[t] + (size_t)cc * ldw] = v[t];
             }
         }
         __syncthreads();
@@ -220,16 +250,16 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
             for (int cc = p0 + 32 + tid; cc < NB; cc += WG) {  // U12 = L11^{-1} A12
                 double x[32];
 #pragma unroll
-                for (int q = 0; q < 32; ++q) x[q] = W[p0 + q + cc * NB];
+                for (int q = 0; q < 32; ++q) x[q] = W[p0 + q + (size_t)cc * ldw];
 #pragma unroll
                 for (int q = 0; q < 32; ++q)
 #pragma unroll
                     for (int r = q + 1; r < 32; ++r) x[r] -= L11[q * 33 + r] * x[q];
 #pragma unroll
-                for (int q = 0; q < 32; ++q) W[p0 + q + cc * NB] = x[q];
+                for (int q = 0; q < 32; ++q) W[p0 + q + (size_t)cc * ldw] = x[q];
             }
             __syncthreads();
-            if constexpr (NB <= 256) {
+            if constexpr (NB <= 256 && RPT == 1) {
                 // A22 -= L21 U12 on FP64 MFMA: L21 (rows p0+32.., 32 cols) and U12 (32 x
                 // trailing cols) staged in LDS, 16x16 output blocks spread over the waves
                 constexpr int LDL = NB + 1;
@@ -263,15 +293,16 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
             } else {
             constexpr int AW = RPT > 1 ? 16 : 32;  // A22 columns per pass (register budget)
             for (int c0 = p0 + 32; c0 < NB; c0 += AW) {  // A22 -= L21 U12
-                for (int e = tid; e < 32 * AW; e += WG) buf[(e / 32) * 33 + e % 32] = W[p0 + e % 32 + (c0 + e / 32) * NB];
+                for (int e = tid; e < 32 * AW; e += WG)
+                    buf[(e / 32) * 33 + e % 32] = W[p0 + e % 32 + (size_t)(c0 + e / 32) * ldw];
                 __syncthreads();
 #pragma unroll
                 for (int u = 0; u < RPT; ++u) {
                     const int r = tid + 256 * u;
-                    if (r < p0 + 32 || r >= NB) continue;
+                    if (r < p0 + 32 || r >= R) continue;
                     double wv[AW];
 #pragma unroll
-                    for (int j = 0; j < AW; ++j) wv[j] = W[r + (c0 + j) * NB];
+                    for (int j = 0; j < AW; ++j) wv[j] = W[r + (size_t)(c0 + j) * ldw];
 #pragma unroll
                     for (int q = 0; q < 32; ++q) {
                         const double lq = P[u][q];
@@ -279,7 +310,7 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
                         for (int j = 0; j < AW; ++j) wv[j] -= lq * buf[j * 33 + q];
                     }
 #pragma unroll
-                    for (int j = 0; j < AW; ++j) W[r + (c0 + j) * NB] = wv[j];
+                    for (int j = 0; j < AW; ++j) W[r + (size_t)(c0 + j) * ldw] = wv[j];
                 }
                 __syncthreads();
             }
@@ -287,9 +318,10 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
         }
         __syncthreads();
     }
-    // permutation of the whole tile: (P A)(r,:) = A(perm[r],:)
+    // permutation of the whole tile (or stacked domain): (P A)(r,:) = A(src[r],:)
+    for (int r = tid; r < R; r += WG) src[r] = r;
+    __syncthreads();
     if (tid == 0) {
-        for (int r = 0; r < NB; ++r) src[r] = r;
         const int *ip = c.ipiv + (size_t)k * NB;
         for (int q = 0; q < NB; ++q) {
             const int p = ip[q];
@@ -298,7 +330,43 @@ LQ_DEV void getrf_diag(const Ctx &c, int k) {
         c.zpiv[k] = g.zp;
     }
     __syncthreads();
-    for (int r = tid; r < NB; r += WG) c.perm[(size_t)k * NB + r] = src[r];
+    if (!dom) {
+        for (int r = tid; r < NB; r += WG) c.perm[(size_t)k * NB + r] = src[r];
+        return;
+    }
+    // Domain: the trailing columns of its rows are interchanged before the LU
+    // branch's Apply (k_domain_swap), so the diagonal tile's own permutation is
+    // the identity; the stacked permutation is kept for that and for the solve.
+    // W_k receives the top block L11\U, the diagonal tile after the domain's
+    // interchanges (Sec. 3.1), for the inverse norm and the decision.
+    for (int r = tid; r < NB; r += WG) c.perm[(size_t)k * NB + r] = r;
+    for (int r = tid; r < R; r += WG) c.dperm[(size_t)k * c.DR + r] = src[r];
+    double *Wk = c.W + (size_t)k * NB * NB;
+    for (int e = tid; e < NB * NB; e += WG) Wk[e] = W[e % NB + (size_t)(e / NB) * ldw];
+    // ||A_ik||_1 of the other domain tiles after the interchanges, from the
+    // original panel values: row r of tile t is stacked row src[t NB + r]
+    double *cs = buf;  // NB column sums
+    for (int t = 1; t < R / NB; ++t) {
+        const int64_t i = k + (int64_t)t * c.dstride;
+        for (int col = w; col < NB; col += 4) {
+            double sum = 0.0;
+            for (int r = l; r < NB; r += 64) {
+                const int so = src[t * NB + r];
+                const S *T = (const S *)c.At + c.toff(k + (int64_t)(so / NB) * c.dstride, k);
+                sum += fabs((double)T[so % NB + (size_t)col * NB]);
+            }
+            sum = wave_sum(sum);
+            if (l == 0) cs[col] = sum;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double tn = 0.0;
+            for (int col = 0; col < NB; ++col) tn = nmax(tn, cs[col]);
+            c.tnorm[i] = tn;
+        }
+        for (int col = tid; col < NB; col += WG) c.away[(size_t)i * NB + col] = 0.0;  // MUMPS: off the domain only
+        __syncthreads();
+    }
 }
 
 // Column sums and column maxima of |A_ik| (one workgroup per tile).
@@ -328,8 +396,18 @@ LQ_DEV void tile_norms(const Ctx &c, int k, int i) {
 
 template <int NB, class S>
 __global__ __launch_bounds__(WG) void k_panel_a(Ctx c, int k) {
-    if (blockIdx.x == 0) getrf_diag<NB, S>(c, k);
-    else tile_norms<NB, S>(c, k, k + (int)blockIdx.x);
+    constexpr size_t S1 = sizeof(GetrfSmem<NB, 1>), S2 = sizeof(GetrfSmem<NB, 2>);
+    __shared__ __attribute__((aligned(16))) char smem[S1 > S2 ? S1 : S2];
+    if (blockIdx.x == 0) {
+        if constexpr (NB <= 256) {
+            if (c.dcount(k) > 1) getrf_core<NB, S, 2>(c, k, smem);  // stacked domain of up to 512 rows
+            else getrf_core<NB, S, 1>(c, k, smem);
+        } else {
+            getrf_core<NB, S, 2>(c, k, smem);
+        }
+    } else if (!c.indom(k, k + (int)blockIdx.x)) {
+        tile_norms<NB, S>(c, k, k + (int)blockIdx.x);  // the domain's tiles are measured after its GEPP
+    }
 }
 
 // ---------------------------------------------------------------------------

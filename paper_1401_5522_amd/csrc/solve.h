@@ -92,6 +92,27 @@ LQ_DEV bool rows_mv(const S *M, const double *v, int nq, int r0, double (&out)[R
     return true;
 }
 
+// LU step with a diagonal domain, part 0: the stacked permutation of the
+// domain's GEPP on the rows of y in its tiles.  grid (1, rhs chunks of 16).
+template <int NB>
+static __global__ __launch_bounds__(WG) void k_fwd_dswap(Ctx c, SolveArgs s, int k) {
+    if (c.dec[k] != 1 || gated(s.gate)) return;
+    const int d = c.dcount(k);
+    if (d < 2) return;
+    constexpr int QC = 16;
+    __shared__ double buf[512 * QC];
+    const int R = d * NB, q0 = blockIdx.y * QC, nq = min(QC, s.nrhs - q0);
+    const int64_t Np = c.n * NB;
+    const int *pm = c.dperm + (size_t)k * c.DR;
+    auto row = [&](int sr) { return (k + (int64_t)(sr / NB) * c.dstride) * NB + sr % NB; };
+    for (int e = threadIdx.x; e < R * nq; e += WG) buf[e] = s.Y[row(e % R) + (q0 + e / R) * Np];
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * nq; e += WG) {
+        const int r = e % R, sr = pm[r];
+        if (sr != r) s.Y[row(r) + (q0 + e / R) * Np] = buf[sr + (e / R) * R];
+    }
+}
+
 // LU step, part 1: z_k = L^{-1} P y_k (L^{-1} from the panel, FP64).
 // grid (nb / RB row blocks, rhs chunks).
 template <int NB>

@@ -64,3 +64,14 @@ def test_factor_rejects_bad_arguments_before_any_gpu_call():
     assert L.luqr_factor(64, C.c_void_p(16), 64, C.byref(o), C.c_void_p(100), 1 << 30, None, C.byref(h)) == -5
     assert L.luqr_factor(64, C.c_void_p(16), 64, C.byref(o), C.c_void_p(256), 10, None, C.byref(h)) == -6
     assert L.luqr_solve(None, 1, None, 1, None) == -1
+
+
+def test_domain_stride_validation_without_gpu():
+    from paper_1401_5522_amd import _lib
+    L = _lib.lib()
+    o, _ = _lib.make_opts(128, domain=2)                 # n = 8: 1 + 7/2 = 4 tiles, 512 rows
+    assert L.luqr_workspace_bytes(1024, C.byref(o)) > 0
+    o, _ = _lib.make_opts(128, domain=1)                 # 8 tiles of 128 rows: more than 512
+    assert L.luqr_workspace_bytes(1024, C.byref(o)) == _lib.LUQR_ERR_UNSUPPORTED
+    o, _ = _lib.make_opts(128, domain=-1)
+    assert L.luqr_workspace_bytes(1024, C.byref(o)) == -2
