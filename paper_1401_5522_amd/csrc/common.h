@@ -20,6 +20,7 @@ constexpr int KRYLOV_MAX = 30;  // largest GMRES basis of luqr_solve_gmres_ir
 enum Prec { P64 = 0, P32 = 1, PB16 = 2 };
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 

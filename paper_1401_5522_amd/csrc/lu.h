@@ -231,7 +231,90 @@ LQ_DEV void lu_update_f32(const float *__restrict__ Aik, const float *__restrict
         }
 }
 
-template <int P> constexpr int upd_occ() { return P == P32 ? 2 : 1; }
+// FP64 storage, nb >= 128: the same 128 x 128 x nb tile product on
+// v_mfma_f64_16x16x4f64.
+//   * K runs in chunks of 16 doubles, staged K-contiguous with a row stride
+//     of 18 doubles (144 bytes, so sixteen lanes' 16-byte reads hit sixteen
+//     disjoint bank groups); A_ik is transposed through registers in 2 x 4
+//     blocks, A_kj columns are K-contiguous already.
+//   * Lane (i16, g) takes K index 8 G + 2 g + s in step s of group G for A and
+//     B alike, so each operand pair comes from one 128-bit LDS read that
+//     serves two MFMAs.
+//   * Four waves of 64 x 64 (4 x 4 blocks of 16 x 16, 64 accumulator
+//     doubles per lane); the next chunk is loaded into registers while the
+//     current one is multiplied: one barrier a chunk.
+// 74 KB of LDS and at most 256 registers: two workgroups per CU.
+constexpr int UPD64_BK = 16, UPD64_LD = UPD64_BK + 2;
+constexpr int upd64_lds_doubles() { return 2 * 2 * 128 * UPD64_LD; }
+
+template <int NB>
+LQ_DEV void lu_update_f64(const double *__restrict__ Aik, const double *__restrict__ Akj, double *__restrict__ C,
+                          int r0, int c0, double *sm) {
+    const int tid = threadIdx.x, l = lane_id(), w = wave_id(), g = l >> 4, i16 = l & 15;
+    const int m0 = (w & 1) * 64, n0 = (w >> 1) * 64;  // the wave's 64 x 64 block
+    // staging: A: rows 2 m2, 2 m2 + 1 at k = 4 kq .. 4 kq + 3; B: column n = tid / 2, k = 8 bh .. 8 bh + 7
+    const int m2 = tid & 63, kq = tid >> 6, bn = tid >> 1, bh = tid & 1;
+    d2 ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ra[u] = *(const d2 *)&Aik[(r0 + 2 * m2) + (size_t)(k0 + 4 * kq + u) * NB];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rb[u] = *(const d2 *)&Akj[(k0 + 8 * bh + 2 * u) + (size_t)(c0 + bn) * NB];
+    };
+    auto store = [&](int buf) {
+        double *As = sm + buf * (2 * 128 * UPD64_LD), *Bs = As + 128 * UPD64_LD;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {  // row 2 m2 + i, k = 4 kq .. 4 kq + 3
+            *(d2 *)&As[(2 * m2 + i) * UPD64_LD + 4 * kq] = (d2){ra[0][i], ra[1][i]};
+            *(d2 *)&As[(2 * m2 + i) * UPD64_LD + 4 * kq + 2] = (d2){ra[2][i], ra[3][i]};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) *(d2 *)&Bs[bn * UPD64_LD + 8 * bh + 2 * u] = rb[u];
+    };
+    d4 acc[4][4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (d4){0.0, 0.0, 0.0, 0.0};
+    load(0);
+    store(0);
+    __syncthreads();
+    constexpr int NCH = NB / UPD64_BK;
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < NCH) load((ch + 1) * UPD64_BK);
+        const double *As = sm + buf * (2 * 128 * UPD64_LD), *Bs = As + 128 * UPD64_LD;
+#pragma unroll
+        for (int G = 0; G < UPD64_BK / 8; ++G) {
+            d2 a[4], bv[4];
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) a[mb] = *(const d2 *)&As[(m0 + 16 * mb + i16) * UPD64_LD + 8 * G + 2 * g];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) bv[nb] = *(const d2 *)&Bs[(n0 + 16 * nb + i16) * UPD64_LD + 8 * G + 2 * g];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][s], bv[nb][s], acc[mb][nb], 0, 0, 0);
+        }
+        if (ch + 1 < NCH) store(buf ^ 1);
+        __syncthreads();
+    }
+    // C -= acc: lane (i16, g) owns rows 16 mb + g + 4 r of column 16 nb + i16
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double *p = &C[(r0 + m0 + 16 * mb + Tr<P64>::drow(g, r)) + (size_t)(c0 + n0 + 16 * nb + i16) * NB];
+                *p = *p - acc[mb][nb][r];
+            }
+}
+
+template <int P> constexpr int upd_occ() { return P == P32 || P == P64 ? 2 : 1; }
 
 // Tile columns j = jlo .. n-1 (grid: (n-k-1) (n-jlo) tiles x PER^2 blocks):
 // jlo = k+1 for the whole update, or the lookahead column k+1 and the rest
@@ -248,6 +331,16 @@ __global__ __launch_bounds__(WG, (upd_occ<P>())) void k_lu_update(Ctx c, int k, 
         const int i = k + 1 + t % rest, j = jlo + t / rest;
         const float *At = (const float *)c.At;
         lu_update_f32<NB>(At + c.toff(i, k), At + c.toff(k, j), (float *)c.At + c.toff(i, j), (sub % PER) * 128,
+                          (sub / PER) * 128, sm);
+        return;
+    } else if constexpr (P == P64 && NB >= 128) {
+        __shared__ __attribute__((aligned(16))) double sm[upd64_lds_doubles()];
+        constexpr int PER = NB / 128;
+        const int rest = (int)c.n - k - 1;
+        const int b = blockIdx.x, sub = b % (PER * PER), t = b / (PER * PER);
+        const int i = k + 1 + t % rest, j = jlo + t / rest;
+        const double *At = (const double *)c.At;
+        lu_update_f64<NB>(At + c.toff(i, k), At + c.toff(k, j), (double *)c.At + c.toff(i, j), (sub % PER) * 128,
                           (sub / PER) * 128, sm);
         return;
     } else {
