@@ -108,7 +108,7 @@ struct Eng {
                 if (rest > 0) k_fwd_lu_b<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
             } else {
                 if (rest > 0) k_fwd_qr_g<NB, S><<<dim3(rest * qs<NB>(), ch), WG, 0, st>>>(c, s, k);
-                k_fwd_qr_chain<NB, S><<<dim3(1, ch), CHAIN_WG, 0, st>>>(c, s, k);
+                k_fwd_qr_chain<NB, S><<<dim3(1, ch), chain_wg<S>(), 0, st>>>(c, s, k);
                 if (rest > 0) k_fwd_qr_u<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
             }
         }

@@ -230,10 +230,68 @@ static __global__ __launch_bounds__(WG) void k_fwd_qr_g(Ctx c, SolveArgs s, int 
 // which is the top half of [z; y_i] <- Q_ik^T [z; y_i] (V = [I; Y_ik]); the
 // bottom half y_i -= Y_ik w_i is independent of the chain and left to part 3.
 // Only the triangular T factors are read inside the chain.
-constexpr int CHAIN_WG = 1024;
+// threads of the chain workgroup: eight waves where T is prefetched into
+// registers (4-byte storage), sixteen otherwise
+template <class S> constexpr int chain_wg() { return sizeof(S) == 4 ? 512 : 1024; }
+
+// w = T^T u for the upper-triangular T of one panel tile, with T's entries
+// taken from registers that were loaded during the previous step of the
+// chain, so the chain waits on no global load (4-byte storage, nb <= 256).
+// The nb/16 groups of sixteen output columns are dealt to the eight waves:
+// group w, and for nb = 256 also group 15 - w, which balances the
+// triangle's rows (group g needs rows 0 .. 16 g + 15: at most 128 for the
+// first, 256 for the second); lane l holds rows 64 m + l of a group.
+template <int NB, class S> struct ChainT {
+    static constexpr int NG = NB / 16;
+    static constexpr bool TWO = NG > 8;
+    static constexpr int M0 = NB >= 128 ? 2 : 1;      // row chunks of group w (16 w + 16 <= 128)
+    static constexpr int M1 = TWO ? NB / 64 : 1;     // row chunks of group NG - 1 - w
+    S t0[M0][16], t1[M1][16];
+    template <int M>
+    LQ_DEV static void load_group(S (&t)[M][16], const S *T, int g) {
+        const int l = lane_id(), r0 = 16 * g;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int cc = 64 * m + l;
+                t[m][j] = (g < NG && cc < NB && cc <= r0 + j) ? T[cc + (size_t)(r0 + j) * NB] : (S)0;
+            }
+    }
+    template <int M>
+    LQ_DEV static void apply_group(const S (&t)[M][16], int g, const double *u, int nq, double *out) {
+        const int l = lane_id(), r0 = 16 * g;
+        if (g >= NG) return;
+        for (int q = 0; q < nq; ++q) {
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int cc = 64 * m + l;
+                const double uc = cc < NB ? u[q * NB + cc] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] += (double)t[m][j] * uc;
+            }
+            const double tot = xreduce16(v);
+            if ((l & 3) == 0) out[q * NB + r0 + ((l >> 2) & 15)] = tot;
+        }
+    }
+    LQ_DEV void load(const S *T) {
+        const int w = (int)(threadIdx.x >> 6);
+        load_group(t0, T, w);
+        if constexpr (TWO) load_group(t1, T, NG - 1 - w);
+    }
+    LQ_DEV void apply(const double *u, int nq, double *out) const {
+        const int w = (int)(threadIdx.x >> 6);
+        apply_group(t0, w, u, nq, out);
+        if constexpr (TWO) apply_group(t1, NG - 1 - w, u, nq, out);
+    }
+};
 
 template <int NB, class S>
-static __global__ __launch_bounds__(CHAIN_WG) void k_fwd_qr_chain(Ctx c, SolveArgs s, int k) {
+static __global__ __launch_bounds__(chain_wg<S>()) void k_fwd_qr_chain(Ctx c, SolveArgs s, int k) {
+    constexpr int CHAIN_WG = chain_wg<S>();
     if (c.dec[k] != 0 || gated(s.gate)) return;
     constexpr int RQ = rq<NB>(), NW = CHAIN_WG / 64;
     constexpr int PER = (NB * RQ + CHAIN_WG - 1) / CHAIN_WG;
@@ -262,6 +320,10 @@ static __global__ __launch_bounds__(CHAIN_WG) void k_fwd_qr_chain(Ctx c, SolveAr
         const int e = tid + p * CHAIN_WG;
         gn[p] = (k + 1 < c.n && e < NB * nq) ? s.G[gidx(k + 1, e)] : 0.0;
     }
+    constexpr bool REG = NB <= 256 && sizeof(S) == 4;  // T of the next tile prefetched into registers
+    ChainT<NB, S> tn;
+    if constexpr (REG)
+        if (k + 1 < c.n) tn.load(Tf + c.tqoff(k + 1, k));
     for (int i = k + 1; i < c.n; ++i) {
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
@@ -274,7 +336,12 @@ static __global__ __launch_bounds__(CHAIN_WG) void k_fwd_qr_chain(Ctx c, SolveAr
             const int e = tid + p * CHAIN_WG;
             gn[p] = (i + 1 < c.n && e < NB * nq) ? s.G[gidx(i + 1, e)] : 0.0;
         }
-        cols_dot<NB, NW, 1, S>(Tf + c.tqoff(i, k), u, nq, w, NB, 0, NB);
+        if constexpr (REG) {
+            tn.apply(u, nq, w);
+            if (i + 1 < c.n) tn.load(Tf + c.tqoff(i + 1, k));
+        } else {
+            cols_dot<NB, NW, 1, S>(Tf + c.tqoff(i, k), u, nq, w, NB, 0, NB);
+        }
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
