@@ -56,9 +56,14 @@ def parse():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 runs (default: --steps; 0 = skip)")
     ap.add_argument("--cpu-N", type=int, default=8192, help="matrix size of the oracle sample (0 = skip)")
-    ap.add_argument("--workload", default="single", choices=("single", "batched"),
+    ap.add_argument("--workload", default="single", choices=("single", "batched", "sweep"),
                     help="single: one large system (default); batched: many small ragged systems in one "
-                         "persistent launch replayed from a graph")
+                         "persistent launch replayed from a graph; sweep: the FP64 path over the matrix "
+                         "types and thresholds of --kinds x --alphas (time, LU fraction, backward error, "
+                         "growth)")
+    ap.add_argument("--kinds", default="gaussian,diag_dominant,growth_prone",
+                    help="sweep: matrix types (inputs.matrix names)")
+    ap.add_argument("--alphas", default="0,0.5,1,4,inf", help="sweep: thresholds")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--input-cache", default="", metavar="PATH",
                     help="raw FP64 file of A: loaded if it exists, else written after generation (lets "
@@ -249,6 +254,48 @@ def batched_inputs(batch, seed, torch):
     return N, kind, As, Bs
 
 
+def run_sweep(args, torch):
+    """FP64 hybrid LU-QR over matrix types x thresholds at one size (the
+    paper's sweep from all-QR to all-LU, Sec. 5.2, Tab. 2): for each run the
+    median time of --steps factor+solve passes, the LU steps taken, the
+    backward error of the solution and the element growth max |U| / max |A|
+    of the final upper-triangular factor (N = 16384, n_b = 256 by default)."""
+    from paper_1401_5522_amd import inputs, solver
+    N, nb = args.N, args.nb
+    rows = []
+    b = torch.from_numpy(inputs.rhs(N, 1, seed=(161,)).reshape(N, 1)).cuda()
+    for kind in args.kinds.split(","):
+        print(f"# generating {kind} N={N}", file=sys.stderr, flush=True)
+        A = torch.from_numpy(inputs.matrix(kind, N, seed=(160,))).cuda()
+        amax = float(A.abs().max())
+        for a in args.alphas.split(","):
+            alpha = float(a)
+            ts = []
+            for it in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f = solver.factor(A, nb, criterion=args.criterion, alpha=alpha, precision="fp64")
+                x = f.solve(b)
+                torch.cuda.synchronize()
+                if it >= args.warmup:
+                    ts.append(time.perf_counter() - t0)
+            dec = f.decisions()[0]
+            st = f.status()
+            F, _ = f.export()
+            growth = float(torch.triu(F).abs().max()) / amax
+            eta = backward_error(A, x, b)
+            ms = 1e3 * float(np.median(ts))
+            rows.append({"kind": kind, "alpha": alpha, "ms": round(ms, 2),
+                         "tflops_2n3_3": round(2.0 * N ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3),
+                         "lu_steps": int(dec.sum()), "steps": int(len(dec)), "eta": eta, "growth": growth,
+                         "nonfinite": int(st.nonfinite)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del f, F, x
+        del A
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": f"FP64 sweep N={N} nb={nb} {args.criterion}", "runs": rows}), flush=True)
+
+
 def run_batched(args, torch):
     from paper_1401_5522_amd import solver
     K, W = args.steps, args.warmup
@@ -350,6 +397,9 @@ def main():
         return
     if args.workload == "batched":
         run_batched(args, torch)
+        return
+    if args.workload == "sweep":
+        run_sweep(args, torch)
         return
     from paper_1401_5522_amd import inputs, solver
     N, nb, prec = args.N, args.nb, args.precision
