@@ -110,8 +110,8 @@ __global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
 
 // Diagonal domain, LU step: the trailing columns j > k of the domain's rows
 // take the stacked permutation of its GEPP, (P D)(s,:) = D(dperm[s],:), so
-// that Apply needs no interchanges of its own (in the domain variant of
-// Sec. 2.1 the Apply step is modified accordingly).  Grid: (n-k-1) tile
+// that Apply needs no interchanges of its own (Sec. 2.1: with this variant
+// Apply works on the domain's interchanged rows).  Grid: (n-k-1) tile
 // columns x NB/16 chunks of 16 columns; a workgroup gathers the domain rows
 // of its chunk into LDS and writes back the rows that move.  BF16 tile maxima:
 // rows only move among the domain's tiles of one column, so their largest
