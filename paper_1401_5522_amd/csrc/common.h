@@ -134,7 +134,9 @@ LQ_DEV double wave_max(double v) {
 template <int ST> LQ_DEV void argmax_step(double &v, int &idx) {
     const double ov = xlane<ST>(v);
     const int oi = xlane<ST>(idx);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    const bool take = (ov > v) | ((ov == v) & (oi < idx));  // selects, no branches
+    v = take ? ov : v;
+    idx = take ? oi : idx;
 }
 // argmax of |value| with the smallest index winning ties; NaN never wins.
 LQ_DEV void wave_argmax(double &v, int &idx) {

@@ -54,7 +54,13 @@ struct Eng {
         for (int k = 0; k < nsteps; ++k) {
             const int rest = n - k - 1;
             if (ev) (void)hipEventRecord(ev[E * k + 0], st);
-            k_panel_a<NB, S><<<n - k, WG, 0, st>>>(c, k);
+            if (rest > 0) k_panel_norms<NB, S><<<rest, WG, 0, st>>>(c, k);
+            if constexpr (NB <= 256) {
+                if (c.dcount(k) > 1) k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);  // up to 512 stacked rows
+                else k_panel_getrf<NB, S, 1><<<1, WG, 0, st>>>(c, k);
+            } else {
+                k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);
+            }
             k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
             k_panel_invnorm<NB><<<(NB / B) * (NB / B), WG, 0, st>>>(c, k);
             DecideArgs a;

@@ -37,102 +37,176 @@ LQ_DEV double wave_nmax(double v) {
 // ---------------------------------------------------------------------------
 template <int NB> constexpr int lu_rpt() { return NB > 256 ? 2 : 1; }
 
+// Per-column exchange area, two buffers (column q uses buffer q & 1, so a
+// thread may start writing column q+1 while others still read column q).
 struct GetrfLds {
-    double bv[4];
-    int bi[4];
-    int dnan;  // the diagonal entry of the column being eliminated is NaN
+    double bv[2][4];
+    int bi[2][4];
+    int dnan[2];          // the diagonal entry of the column being eliminated is NaN
+    double cand[2][4][32];// each wave's best row of the 32-column panel
+    double rowA[2][32];   // the diagonal row
     int piv[32];
-    int zp;
     int tcnt;
     int trow[64], tsrc[64];
-    double rowA[32], rowB[32];
 };
 
-template <int RPT, int Q>
-LQ_DEV void lu_column(double (&P)[RPT][32], int p0, int R, GetrfLds *g) {
+// The 32 columns of a panel, one per iteration and one barrier each: before
+// the barrier each wave's winner of the argmax writes its whole row (and the
+// owner of the diagonal row writes that one), so after it every thread takes
+// the pivot row from the winning wave's slot without a second round trip.
+// The thread's rows sit in registers in rotated order: at column q, P[u][j]
+// holds panel column (q + j) mod 32, so the column being eliminated is always
+// P[u][0] and one small loop body serves every column; 32 rotations restore
+// the original order.
+template <int RPT>
+LQ_DEV void lu_panel_columns(double (&P)[RPT][32], int p0, int R, GetrfLds *g, int &zp) {
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
-    const int col = p0 + Q;
-    double v = -1.0;
-    int idx = 0x7fffffff;
+#pragma unroll 1
+    for (int q = 0; q < 32; ++q) {
+        const int col = p0 + q, buf = q & 1;
+        const int act = 32 - q;  // positions 0 .. act-1 hold columns q .. 31
+        double v = -1.0;
+        int idx = 0x7fffffff;
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {  // rows ascending within the thread
-        const int r = tid + 256 * u;
-        if (r >= col && r < R) {
-            const double a = fabs(P[u][Q]);
-            if (a > v) { v = a; idx = r; }
+        for (int u = 0; u < RPT; ++u) {  // rows ascending within the thread
+            const int r = tid + 256 * u;
+            if (r >= col && r < R) {
+                const double a = fabs(P[u][0]);
+                if (a > v) { v = a; idx = r; }
+            }
+            if (r == col) {
+                g->dnan[buf] = P[u][0] != P[u][0];
+#pragma unroll
+                for (int j = 0; j < 32; ++j) g->rowA[buf][j] = P[u][j];
+            }
         }
-        if (r == col) g->dnan = P[u][Q] != P[u][Q];
-    }
-    wave_argmax(v, idx);
-    if (l == 0) { g->bv[w] = v; g->bi[w] = idx; }
-    __syncthreads();  // A
-    v = g->bv[0];
-    idx = g->bi[0];
+        wave_argmax(v, idx);
+        if (idx != 0x7fffffff && tid == (idx & 255)) {  // this thread holds the wave's best row
 #pragma unroll
-    for (int q = 1; q < 4; ++q) {
-        const double ov = g->bv[q];
-        const int oi = g->bi[q];
-        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-    }
-    // The scan that defines the pivot starts at the diagonal and moves to a
-    // later row only if its magnitude is strictly larger, so a NaN on the
-    // diagonal stays the pivot (and NaNs below it are never chosen); a column
-    // of exact zeros below and on the diagonal is skipped (no elimination).
-    const bool dnan = g->dnan != 0;
-    const bool zero = !dnan && !(v > 0.0);
-    const int piv = (zero || dnan) ? col : idx;
-    if (tid == 0) {
-        g->piv[Q] = piv;
-        if (zero && g->zp == 0) g->zp = col + 1;
-    }
+            for (int u = 0; u < RPT; ++u)
+                if ((idx >> 8) == u) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        const int r = tid + 256 * u;
-        if (r == col) {
-#pragma unroll
-            for (int j = 0; j < 32; ++j) g->rowA[j] = P[u][j];
+                    for (int j = 0; j < 32; ++j) g->cand[buf][w][j] = P[u][j];
+                }
         }
-        if (r == piv) {
+        if (l == 0) { g->bv[buf][w] = v; g->bi[buf][w] = idx; }
+        __syncthreads();
+        double wv[4];
+        int wi[4];
 #pragma unroll
-            for (int j = 0; j < 32; ++j) g->rowB[j] = P[u][j];
+        for (int t = 0; t < 4; ++t) { wv[t] = g->bv[buf][t]; wi[t] = g->bi[buf][t]; }
+        const bool dnan = g->dnan[buf] != 0;
+        v = wv[0];
+        idx = wi[0];
+        int win = 0;
+#pragma unroll
+        for (int t = 1; t < 4; ++t) {
+            const bool take = (wv[t] > v) | ((wv[t] == v) & (wi[t] < idx));
+            v = take ? wv[t] : v;
+            idx = take ? wi[t] : idx;
+            win = take ? t : win;
         }
-    }
-    __syncthreads();  // B: rows col and piv exchanged through LDS
-    if (!zero) {
-        const double pv = g->rowB[Q];
+        // The scan that defines the pivot starts at the diagonal and moves to
+        // a later row only if its magnitude is strictly larger, so a NaN on
+        // the diagonal stays the pivot (and NaNs below it are never chosen); a
+        // column of exact zeros on and below the diagonal is skipped.
+        const bool zero = !dnan && !(v > 0.0);
+        const int piv = (zero || dnan) ? col : idx;
+        if (tid == 0) g->piv[q] = piv;
+        zp = (zero && zp == 0) ? col + 1 : zp;  // the same in every thread
+        if (!zero) {
+            const double *rowA = g->rowA[buf];
+            const double *rowB = piv == col ? rowA : g->cand[buf][win];
+            const double pv = rowB[0];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int r = tid + 256 * u;
+                if (r == col || r == piv) {  // the interchange
+                    const double *sr = r == col ? rowB : rowA;
+#pragma unroll
+                    for (int j = 0; j < 32; ++j) P[u][j] = sr[j];
+                }
+                if (r > col && r < R) {
+                    const double lr = P[u][0] / pv;
+                    P[u][0] = lr;
+                    // positions act.. hold earlier columns' multipliers: their
+                    // factor is zero (lr is finite whenever the step is kept:
+                    // a NaN pivot sends the step to QR, which discards W)
+#pragma unroll
+                    for (int j = 1; j < 32; ++j) {
+                        const long long mk = j < act ? -1ll : 0ll;  // bit mask: no branch per position
+                        P[u][j] -= lr * __longlong_as_double(__double_as_longlong(rowB[j]) & mk);
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
-            const int r = tid + 256 * u;
-            if (r == col) {
+            const double t0 = P[u][0];
 #pragma unroll
-                for (int j = 0; j < 32; ++j) P[u][j] = g->rowB[j];
-            } else if (r == piv) {
-#pragma unroll
-                for (int j = 0; j < 32; ++j) P[u][j] = g->rowA[j];
-            }
-            if (r > col && r < R) {
-                const double lr = P[u][Q] / pv;
-                P[u][Q] = lr;
-#pragma unroll
-                for (int j = Q + 1; j < 32; ++j) P[u][j] -= lr * g->rowB[j];
-            }
+            for (int j = 0; j < 31; ++j) P[u][j] = P[u][j + 1];
+            P[u][31] = t0;
         }
     }
 }
 
-template <int RPT, int... Qs>
-LQ_DEV void lu_columns(double (&P)[RPT][32], int p0, int R, GetrfLds *g, std::integer_sequence<int, Qs...>) {
-    (lu_column<RPT, Qs>(P, p0, R, g), ...);
+// The row moves of one panel's 32 interchanges (row p0 + q with piv[q], in
+// order), built by one wave with a lane per touched row: lanes 0..31 stand
+// for rows p0..p0+31, lane 32 + q for piv[q] when it lies below the panel and
+// first appears at q.  Each lane carries the position (before the panel) of
+// the row now at its own position; the interchanges pass these between lanes
+// in registers.  Result: trow[t] receives row tsrc[t], and the running
+// permutation gsrc (position -> original row) is composed with the moves.
+LQ_DEV void panel_moves(int p0, GetrfLds &g, int *gsrc) {
+    const int l = lane_id();
+    int pv[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) pv[q] = g.piv[q];  // the same in every lane
+    const int b = g.piv[l & 31];
+    int first = 32;
+#pragma unroll
+    for (int q = 31; q >= 0; --q) first = pv[q] == b ? q : first;
+    const bool valid = l < 32 || (b >= p0 + 32 && first == l - 32);
+    const int key = l < 32 ? p0 + l : b;
+    int cont = key;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const int a = p0 + q, bq = __builtin_amdgcn_readfirstlane(pv[q]);
+        if (bq != a) {
+            const int lb = bq < p0 + 32 ? bq - p0 : 32 + __builtin_amdgcn_readlane(first, 32 + q);
+            const int ca = __builtin_amdgcn_readlane(cont, q), cb = __builtin_amdgcn_readlane(cont, lb);
+            cont = l == q ? cb : (l == lb ? ca : cont);
+        }
+    }
+    const bool mv = valid && cont != key;
+    const unsigned long long bal = __ballot(mv);
+    const int pos = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+    const int gs = mv ? gsrc[cont] : 0;  // every lane reads before any writes
+    if (mv) {
+        g.trow[pos] = key;
+        g.tsrc[pos] = cont;
+        gsrc[key] = gs;
+    }
+    if (l == 0) g.tcnt = __popcll(bal);
 }
 
 // The same elimination runs on the diagonal tile alone (R = NB rows, W the
 // step's copy, ld NB) or on the stacked diagonal domain (R = d NB rows of the
 // tiles k, k+p, ..., W = c.WD, ld DR): the pivot of each column is searched
 // over all R rows.  RPT = rows per thread / 256 >= R / 256.
+// The tile variant (RPT = 1, n_b <= 256) stages L21 whole and U12 in chunks
+// of UC columns for its MFMA update, with L11 in the U12 area (it is done with
+// before U12 is staged): about 80 KB at n_b = 256, so the workgroup fits on a
+// compute unit beside a trailing-update workgroup of the previous step.
 template <int NB, int RPT> struct GetrfSmem {
-    static constexpr int BUFN = (NB <= 256 && RPT == 1) ? 32 * (NB + 1) + NB * 33 : 32 * 33;
+    static constexpr bool MF = NB <= 256 && RPT == 1;  // A22 on FP64 MFMA
+    static constexpr int LDL = NB - 31;                 // L21 rows (at most NB - 32), odd stride
+    static constexpr int UC = 64;                       // U12 columns per staged chunk
+    static constexpr int UBN = UC * 33 > 32 * 33 ? UC * 33 : 32 * 33;
+    static constexpr int BUFN = MF ? 32 * LDL + UBN : 32 * 33;
     double buf[BUFN];  // L21 / U12 staging of the trailing update
-    double L11[32 * 33];
+    double L11x[MF ? 1 : 32 * 33];
+    LQ_DEV double *L11() { if constexpr (MF) return buf + 32 * LDL; else return L11x; }
     int src[256 * RPT];
     unsigned long long lmx[NB];
     GetrfLds g;
@@ -144,7 +218,7 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
     const int R = dom ? c.dcount(k) * NB : NB;
     const int ldw = dom ? c.DR : NB;
     GetrfSmem<NB, RPT> &sm = *(GetrfSmem<NB, RPT> *)smem;
-    double *buf = sm.buf, *L11 = sm.L11;
+    double *buf = sm.buf, *L11 = sm.L11();
     int *src = sm.src;
     unsigned long long *lmx = sm.lmx;
     GetrfLds &g = sm.g;
@@ -152,7 +226,8 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
     double *W = dom ? c.WD : c.W + (size_t)k * NB * NB;
     const S *A = (const S *)c.At + c.toff(k, k);
     for (int e = tid; e < NB; e += WG) lmx[e] = 0ull;
-    if (tid == 0) g.zp = 0;
+    for (int r = tid; r < R; r += WG) src[r] = r;  // running permutation of the rows
+    int zp = 0;                                     // first zero pivot column + 1
     __syncthreads();
     if (dom) {
         // stacked copy of the domain's tiles and its column maxima (MUMPS
@@ -169,25 +244,35 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
             if (l == 0) lmx[col] = (unsigned long long)__double_as_longlong(m);
         }
     } else {
-    // copy A_kk -> W (FP64) and its column maxima (MUMPS local_max)
-    for (int e0 = 0; e0 < NB * NB; e0 += 8 * WG) {
-        double a[8];
+    // copy A_kk -> W (FP64) and its column maxima (MUMPS local_max): four
+    // consecutive entries of one column per load, 16 loads in flight
+    struct alignas(4 * sizeof(S)) S4 { S v[4]; };
+    constexpr int NV = NB * NB / 4;
+    for (int v0 = 0; v0 < NV; v0 += 16 * WG) {
+        S4 a[16];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int e = e0 + t * WG + tid;
-            a[t] = e < NB * NB ? (double)A[e] : 0.0;
+        for (int t = 0; t < 16; ++t) {
+            const int vi = v0 + t * WG + tid;
+            if (vi < NV) a[t] = ((const S4 *)A)[vi];
         }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int e = e0 + t * WG + tid;
-            if (e < NB * NB) W[e] = a[t];
-            double m = fabs(a[t]);
+        for (int t = 0; t < 16; ++t) {
+            const int vi = v0 + t * WG + tid;
+            double m = 0.0;
+            if (vi < NV) {
+                d2 x0, x1;
+                x0[0] = (double)a[t].v[0]; x0[1] = (double)a[t].v[1];
+                x1[0] = (double)a[t].v[2]; x1[1] = (double)a[t].v[3];
+                ((d2 *)W)[2 * vi] = x0;
+                ((d2 *)W)[2 * vi + 1] = x1;
+                m = nmax(nmax(fabs(x0[0]), fabs(x0[1])), nmax(fabs(x1[0]), fabs(x1[1])));
+            }
             // non-negative doubles (and NaN above them) order as their bit patterns
-            if constexpr (NB >= 64) {
-                m = wave_nmax(m);  // a wave covers 64 consecutive rows of one column
-                if (l == 0 && e < NB * NB) atomicMax(&lmx[e / NB], (unsigned long long)__double_as_longlong(m));
-            } else if (e < NB * NB) {  // a wave spans several columns: one atomic per element
-                atomicMax(&lmx[e / NB], (unsigned long long)__double_as_longlong(m));
+            if constexpr (NB >= 256) {
+                m = wave_nmax(m);  // a wave covers 256 consecutive rows of one column
+                if (l == 0 && vi < NV) atomicMax(&lmx[4 * vi / NB], (unsigned long long)__double_as_longlong(m));
+            } else if (vi < NV) {
+                atomicMax(&lmx[4 * vi / NB], (unsigned long long)__double_as_longlong(m));
             }
         }
     }
@@ -202,7 +287,8 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
 #pragma unroll
             for (int j = 0; j < 32; ++j) P[u][j] = (r >= p0 && r < R) ? W[r + (size_t)(p0 + j) * ldw] : 0.0;
         }
-        lu_columns<RPT>(P, p0, R, &g, std::make_integer_sequence<int, 32>{});
+        lu_panel_columns<RPT>(P, p0, R, &g, zp);
+        __syncthreads();  // the last column's pivot is recorded
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
             const int r = tid + 256 * u;
@@ -214,35 +300,38 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
 #pragma unroll
                 for (int j = 0; j < 32; ++j) L11[j * 33 + (r - p0)] = P[u][j];
             }
+            if constexpr (GetrfSmem<NB, RPT>::MF) {  // L21 for the MFMA update, row r at r - (p0 + 32)
+                if (r >= p0 + 32 && r < NB) {
+#pragma unroll
+                    for (int j = 0; j < 32; ++j) buf[j * GetrfSmem<NB, RPT>::LDL + r - p0 - 32] = P[u][j];
+                }
+            }
         }
         if (tid < 32) c.ipiv[(size_t)k * NB + p0 + tid] = g.piv[tid];
-        // rows moved by the panel's interchanges: trow[t] receives row tsrc[t]
-        for (int r = p0 + tid; r < R; r += WG) src[r] = r;
+        if (w == 0) panel_moves(p0, g, src);  // rows moved by the panel's interchanges
         __syncthreads();
-        if (tid == 0) {
-            for (int q = 0; q < 32; ++q) {
-                const int a = p0 + q, b = g.piv[q];
-                const int t = src[a]; src[a] = src[b]; src[b] = t;
-            }
-            int cnt = 0;
-            for (int q = 0; q < 32; ++q) {
-                const int a = p0 + q, b = g.piv[q];
-                if (src[a] != a) { g.trow[cnt] = a; g.tsrc[cnt] = src[a]; src[a] = a; ++cnt; }
-                if (b != a && src[b] != b) { g.trow[cnt] = b; g.tsrc[cnt] = src[b]; src[b] = b; ++cnt; }
-            }
-            g.tcnt = cnt;
-        }
-        __syncthreads();
-        {
+        {   // the panel's interchanges on the columns outside it: a wave per
+            // column (its moved rows lie in one column), a lane per moved row;
+            // wave w takes columns w, w + 4, ..., GB of them loaded before any
+            // is written
+            constexpr int NC = NB / 4, GB = NC < 32 ? NC : 32;
             const int cnt = g.tcnt;
-            for (int cc = tid; cc < NB; cc += WG) {  // columns outside the panel
-                if (cc >= p0 && cc < p0 + 32) continue;
-                double v[64];
+            const int ts = l < cnt ? g.tsrc[l] : 0, tr = l < cnt ? g.trow[l] : 0;
+#pragma unroll 1
+            for (int b0 = 0; b0 < NC; b0 += GB) {
+                double v[GB];
 #pragma unroll
-                for (int t = 0; t < 64; ++t) v[t] = t < cnt ? W[g.tsrc[t] + (size_t)cc * ldw] : 0.0;
+                for (int b = 0; b < GB; ++b) {
+                    const int cc = 4 * (b0 + b) + w;
+                    const bool mv = l < cnt && !(cc >= p0 && cc < p0 + 32);
+                    v[b] = mv ? W[ts + (size_t)cc * ldw] : 0.0;
+                }
 #pragma unroll
-                for (int t = 0; t < 64; ++t)
-                    if (t < cnt) W[g.trow[t] + (size_t)cc * ldw] = v[t];
+                for (int b = 0; b < GB; ++b) {
+                    const int cc = 4 * (b0 + b) + w;
+                    const bool mv = l < cnt && !(cc >= p0 && cc < p0 + 32);
+                    if (mv) W[tr + (size_t)cc * ldw] = v[b];
+                }
             }
         }
         __syncthreads();
@@ -252,44 +341,70 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
 #pragma unroll
                 for (int q = 0; q < 32; ++q) x[q] = W[p0 + q + (size_t)cc * ldw];
 #pragma unroll
-                for (int q = 0; q < 32; ++q)
+                for (int q = 0; q < 32; ++q) {
 #pragma unroll
                     for (int r = q + 1; r < 32; ++r) x[r] -= L11[q * 33 + r] * x[q];
+                    // keep the scheduler from hoisting every L11 load (register pressure)
+                    if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                }
 #pragma unroll
                 for (int q = 0; q < 32; ++q) W[p0 + q + (size_t)cc * ldw] = x[q];
             }
             __syncthreads();
-            if constexpr (NB <= 256 && RPT == 1) {
-                // A22 -= L21 U12 on FP64 MFMA: L21 (rows p0+32.., 32 cols) and U12 (32 x
-                // trailing cols) staged in LDS, 16x16 output blocks spread over the waves
-                constexpr int LDL = NB + 1;
-                double *Ls = buf;                 // [32][LDL]
-                double *Ub = buf + 32 * LDL;      // [ncol][33]
+            if constexpr (GetrfSmem<NB, RPT>::MF) {
+                // A22 -= L21 U12 on FP64 MFMA: L21 (rows p0+32.., 32 cols, staged in LDS
+                // with the panel's write-back), U12 in chunks of UC columns
+                constexpr int LDL = GetrfSmem<NB, RPT>::LDL, UC = GetrfSmem<NB, RPT>::UC;
+                double *Ls = buf;                 // [32][LDL], row r at r - r0
+                double *Ub = buf + 32 * LDL;      // [UC][33]
                 const int r0 = p0 + 32, m = NB - r0;
-#pragma unroll
-                for (int u = 0; u < RPT; ++u) {
-                    const int r = tid + 256 * u;
-                    if (r >= r0 && r < NB) {
-#pragma unroll
-                        for (int q = 0; q < 32; ++q) Ls[q * LDL + r] = P[u][q];
-                    }
-                }
-                for (int e = tid; e < 32 * m; e += WG) Ub[(e / 32) * 33 + e % 32] = W[p0 + e % 32 + (r0 + e / 32) * NB];
-                __syncthreads();
                 const int nbk = m / 16;
                 const int gq = l >> 4, i16 = l & 15;
-                for (int blk = w; blk < nbk * nbk; blk += 4) {
-                    const int br = r0 + 16 * (blk % nbk), bc = 16 * (blk / nbk);
-                    d4 acc;
+                for (int c0 = r0; c0 < NB; c0 += UC) {
+                    const int nc = NB - c0 < UC ? NB - c0 : UC;
+                    for (int e = tid; e < 32 * nc; e += WG) Ub[(e / 32) * 33 + e % 32] = W[p0 + e % 32 + (c0 + e / 32) * NB];
+                    __syncthreads();
+                    // a wave takes 16-row blocks w, w + 4, ... across the chunk's
+                    // columns; the chunk's B operands stay in registers for all of them
+                    const int ncb = nc / 16;
+                    double bop[UC / 16][8];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[r] = W[(br + Tr<P64>::drow(gq, r)) + (r0 + bc + i16) * NB];
+                    for (int cb = 0; cb < UC / 16; ++cb)
 #pragma unroll
-                    for (int ks = 0; ks < 8; ++ks)
-                        acc = Tr<P64>::mma(-Ls[(4 * ks + gq) * LDL + br + i16], Ub[(bc + i16) * 33 + 4 * ks + gq], acc);
+                        for (int ks = 0; ks < 8; ++ks)
+                            bop[cb][ks] = cb < ncb ? Ub[(16 * cb + i16) * 33 + 4 * ks + gq] : 0.0;
+                    // the next row block's C tiles are loaded while this one's are computed
+                    d4 cur[UC / 16], nxt[UC / 16];
+                    auto load_c = [&](int rb, d4 (&cv)[UC / 16]) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) W[(br + Tr<P64>::drow(gq, r)) + (r0 + bc + i16) * NB] = acc[r];
+                        for (int cb = 0; cb < UC / 16; ++cb)
+                            if (cb < ncb && rb < nbk) {
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+                                    cv[cb][r] = W[(r0 + 16 * rb + Tr<P64>::drow(gq, r)) + (c0 + 16 * cb + i16) * NB];
+                            }
+                    };
+                    load_c(w, cur);
+                    for (int rb = w; rb < nbk; rb += 4) {
+                        const int br = r0 + 16 * rb;
+                        load_c(rb + 4, nxt);
+                        double aop[8];
+#pragma unroll
+                        for (int ks = 0; ks < 8; ++ks) aop[ks] = -Ls[(4 * ks + gq) * LDL + br - r0 + i16];
+#pragma unroll
+                        for (int cb = 0; cb < UC / 16; ++cb)
+                            if (cb < ncb) {
+#pragma unroll
+                                for (int ks = 0; ks < 8; ++ks) cur[cb] = Tr<P64>::mma(aop[ks], bop[cb][ks], cur[cb]);
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+                                    W[(br + Tr<P64>::drow(gq, r)) + (c0 + 16 * cb + i16) * NB] = cur[cb][r];
+                            }
+#pragma unroll
+                        for (int cb = 0; cb < UC / 16; ++cb) cur[cb] = nxt[cb];
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             } else {
             constexpr int AW = RPT > 1 ? 16 : 32;  // A22 columns per pass (register budget)
             for (int c0 = p0 + 32; c0 < NB; c0 += AW) {  // A22 -= L21 U12
@@ -318,18 +433,9 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
         }
         __syncthreads();
     }
-    // permutation of the whole tile (or stacked domain): (P A)(r,:) = A(src[r],:)
-    for (int r = tid; r < R; r += WG) src[r] = r;
-    __syncthreads();
-    if (tid == 0) {
-        const int *ip = c.ipiv + (size_t)k * NB;
-        for (int q = 0; q < NB; ++q) {
-            const int p = ip[q];
-            const int t = src[q]; src[q] = src[p]; src[p] = t;
-        }
-        c.zpiv[k] = g.zp;
-    }
-    __syncthreads();
+    // permutation of the whole tile (or stacked domain): (P A)(r,:) = A(src[r],:),
+    // composed panel by panel above
+    if (tid == 0) c.zpiv[k] = zp;
     if (!dom) {
         for (int r = tid; r < NB; r += WG) c.perm[(size_t)k * NB + r] = src[r];
         return;
@@ -369,22 +475,35 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
     }
 }
 
-// Column sums and column maxima of |A_ik| (one workgroup per tile).
+// Column sums and column maxima of |A_ik| (one workgroup per tile).  A wave
+// takes columns w, w + 4, ...; CPW of them are loaded before any is reduced,
+// so that enough loads are in flight to cover the memory latency.
 template <int NB, class S>
 LQ_DEV void tile_norms(const Ctx &c, int k, int i) {
     __shared__ double cs[NB];
     const int l = lane_id(), w = wave_id();
     const S *A = (const S *)c.At + c.toff(i, k);
-    for (int col = w; col < NB; col += 4) {
-        double sum = 0.0, mx = 0.0;
-        for (int r = l; r < NB; r += 64) {
-            double a = fabs((double)A[r + col * NB]);
-            sum += a;
-            mx = nmax(mx, a);
+    constexpr int RPL = NB >= 64 ? NB / 64 : 1;  // rows per lane
+    constexpr int CPW = NB >= 256 ? 8 : 16;      // columns per wave in flight
+    for (int c0 = w; c0 < NB; c0 += 4 * CPW) {
+        double a[CPW][RPL];
+#pragma unroll
+        for (int t = 0; t < CPW; ++t)
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) {
+                const int col = c0 + 4 * t, r = l + 64 * u;
+                a[t][u] = (col < NB && r < NB) ? fabs((double)A[r + col * NB]) : 0.0;
+            }
+#pragma unroll
+        for (int t = 0; t < CPW; ++t) {
+            double sum = 0.0, mx = 0.0;
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) { sum += a[t][u]; mx = nmax(mx, a[t][u]); }
+            sum = wave_sum(sum);
+            mx = wave_nmax(mx);
+            const int col = c0 + 4 * t;
+            if (l == 0 && col < NB) { cs[col] = sum; c.away[(size_t)i * NB + col] = mx; }
         }
-        sum = wave_sum(sum);
-        mx = wave_nmax(mx);
-        if (l == 0) { cs[col] = sum; c.away[(size_t)i * NB + col] = mx; }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -394,20 +513,23 @@ LQ_DEV void tile_norms(const Ctx &c, int k, int i) {
     }
 }
 
+// Norms of the tiles below the diagonal in tile column k, one workgroup per
+// tile (the tiles of a diagonal domain are measured after its elimination).
 template <int NB, class S>
-__global__ __launch_bounds__(WG) void k_panel_a(Ctx c, int k) {
-    constexpr size_t S1 = sizeof(GetrfSmem<NB, 1>), S2 = sizeof(GetrfSmem<NB, 2>);
-    __shared__ __attribute__((aligned(16))) char smem[S1 > S2 ? S1 : S2];
-    if (blockIdx.x == 0) {
-        if constexpr (NB <= 256) {
-            if (c.dcount(k) > 1) getrf_core<NB, S, 2>(c, k, smem);  // stacked domain of up to 512 rows
-            else getrf_core<NB, S, 1>(c, k, smem);
-        } else {
-            getrf_core<NB, S, 2>(c, k, smem);
-        }
-    } else if (!c.indom(k, k + (int)blockIdx.x)) {
-        tile_norms<NB, S>(c, k, k + (int)blockIdx.x);  // the domain's tiles are measured after its GEPP
-    }
+__global__ __launch_bounds__(WG) void k_panel_norms(Ctx c, int k) {
+    const int i = k + 1 + (int)blockIdx.x;
+    if (!c.indom(k, i)) tile_norms<NB, S>(c, k, i);
+}
+
+// GEPP of the diagonal tile (RPT = 1) or of the stacked diagonal domain and
+// of 512-row tiles (RPT = 2): one workgroup, launched apart from the norms so
+// that its LDS and register needs do not fall on every tile's workgroup; the
+// tile variant is held to half a SIMD's registers, so that it fits on a compute
+// unit beside a trailing-update workgroup of the previous step.
+template <int NB, class S, int RPT>
+__global__ __launch_bounds__(WG, RPT == 1 ? 2 : 1) void k_panel_getrf(Ctx c, int k) {
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(GetrfSmem<NB, RPT>)];
+    getrf_core<NB, S, RPT>(c, k, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,11 +645,12 @@ __global__ __launch_bounds__(WG) void k_panel_decide(Ctx c, int k, DecideArgs a)
         inv = nmax(inv, s);
     }
     red[tid] = inv;
-    for (int j = tid; j < NB; j += WG) {
-        double v = 0.0;
-        for (int i = k + 1; i < c.n; ++i) v = nmax(v, c.away[(size_t)i * NB + j]);
-        awayj[j] = v;
-    }
+    if (a.crit == LUQR_CRIT_MUMPS)
+        for (int j = tid; j < NB; j += WG) {
+            double v = 0.0;
+            for (int i = k + 1; i < c.n; ++i) v = nmax(v, c.away[(size_t)i * NB + j]);
+            awayj[j] = v;
+        }
     __syncthreads();
     if (tid != 0) return;
     for (int t = 1; t < WG; ++t) inv = nmax(inv, red[t]);
