@@ -106,7 +106,18 @@ struct Eng {
         const int n = (int)c.n;
         const unsigned ch = (unsigned)((s.nrhs + rq<NB>() - 1) / rq<NB>());
         constexpr int RPT = NB / mv_rb<NB>();  // row blocks per tile
-        for (int k = 0; k < n; ++k) {
+        bool wave = false;
+        if constexpr (NB == 256 && sizeof(S) == 4) {
+            // the forward pass as one wavefront launch; the tile counters reuse
+            // the QR steps' flags (n * nb/IB ints, free once the factorization is done)
+            const int wch = (s.nrhs + FW_RQ - 1) / FW_RQ;
+            if (c.dstride == 0 && wch <= 4) {
+                k_fill_int<<<nblk((int64_t)n * wch), WG, 0, st>>>(c.flags, (int64_t)n * wch, 0);
+                k_fwd_wave<NB, S><<<dim3(n, wch), FW_WG, 0, st>>>(c, s, c.flags);
+                wave = true;
+            }
+        }
+        for (int k = 0; k < n && !wave; ++k) {
             const int rest = n - k - 1;
             if (hdec[k] == 1) {
                 if (c.dcount(k) > 1) k_fwd_dswap<NB><<<dim3(1, (unsigned)((s.nrhs + 15) / 16)), WG, 0, st>>>(c, s, k);
@@ -114,7 +125,7 @@ struct Eng {
                 if (rest > 0) k_fwd_lu_b<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
             } else {
                 if (rest > 0) k_fwd_qr_g<NB, S><<<dim3(rest * qs<NB>(), ch), WG, 0, st>>>(c, s, k);
-                k_fwd_qr_chain<NB, S><<<dim3(1, ch), chain_wg<S>(), 0, st>>>(c, s, k);
+                k_fwd_qr_chain<NB, S><<<dim3(1, ch), chain_wg<NB, S>(), 0, st>>>(c, s, k);
                 if (rest > 0) k_fwd_qr_u<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
             }
         }

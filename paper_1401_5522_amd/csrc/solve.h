@@ -230,68 +230,119 @@ static __global__ __launch_bounds__(WG) void k_fwd_qr_g(Ctx c, SolveArgs s, int 
 // which is the top half of [z; y_i] <- Q_ik^T [z; y_i] (V = [I; Y_ik]); the
 // bottom half y_i -= Y_ik w_i is independent of the chain and left to part 3.
 // Only the triangular T factors are read inside the chain.
-// threads of the chain workgroup: eight waves where T is prefetched into
-// registers (4-byte storage), sixteen otherwise
-template <class S> constexpr int chain_wg() { return sizeof(S) == 4 ? 512 : 1024; }
+// threads of the chain workgroup: eight waves for 4-byte storage (T read into
+// registers for n_b <= 256), sixteen for 8-byte storage (T read from memory:
+// its registers would not fit beside the rest)
+template <int NB, class S> constexpr int chain_wg() { return sizeof(S) == 4 ? 512 : 1024; }
 
-// w = T^T u for the upper-triangular T of one panel tile, with T's entries
-// taken from registers that were loaded during the previous step of the
-// chain, so the chain waits on no global load (4-byte storage, nb <= 256).
-// The nb/16 groups of sixteen output columns are dealt to the eight waves:
-// group w, and for nb = 256 also group 15 - w, which balances the
-// triangle's rows (group g needs rows 0 .. 16 g + 15: at most 128 for the
-// first, 256 for the second); lane l holds rows 64 m + l of a group.
-template <int NB, class S> struct ChainT {
+// Buffer loads of a tile: one register holds the lane's offset and each
+// load adds a wave-uniform offset from a scalar register, so a run of loads
+// in flight costs no address registers per load (with 64-bit addresses it
+// cost two each).  Dword 3 is the CDNA raw-buffer format word (32-bit data);
+// offsets past the tile read as zero.
+LQ_DEV __amdgpu_buffer_rsrc_t tile_rsrc(const float *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, bytes, 0x00020000);
+}
+LQ_DEV f4 tile_load4(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+// 16-byte register vector of the storage type
+template <class S> struct V16t;
+template <> struct V16t<float> { typedef f4 T; };
+template <class S> using V16 = typename V16t<S>::T;
+
+// w = T^T u for the upper-triangular T of one panel tile (4-byte storage,
+// n_b <= 256), with
+// T's entries held in registers, loaded one or two steps of the chain ahead,
+// so the chain waits on no global load.  The n_b/16 groups of sixteen output
+// columns are dealt to the eight waves: group w and, for n_b = 256, group
+// 15 - w (group g needs rows 0 .. 16 g + 15, so the pair balances the
+// triangle).  Lane l holds, for output column q = 16 g + 8 h + (l >> 3)
+// (h = 0, 1), the rows p = CH m + VE (l & 7) .. + VE - 1 of chunk m: each
+// load reads VE consecutive entries (16 bytes) of a column, and one load
+// instruction covers eight columns with whole 128-byte lines.  The eight
+// lanes of a column are summed with three lane exchanges.
+template <int NB, class S> struct ChainR {
+    static constexpr int VE = 16 / (int)sizeof(S);  // entries per 16-byte load
+    static constexpr int CH = 8 * VE;               // rows per chunk
     static constexpr int NG = NB / 16;
-    static constexpr bool TWO = NG > 8;
-    static constexpr int M0 = NB >= 128 ? 2 : 1;      // row chunks of group w (16 w + 16 <= 128)
-    static constexpr int M1 = TWO ? NB / 64 : 1;     // row chunks of group NG - 1 - w
-    S t0[M0][16], t1[M1][16];
-    template <int M>
-    LQ_DEV static void load_group(S (&t)[M][16], const S *T, int g) {
-        const int l = lane_id(), r0 = 16 * g;
-#pragma unroll
-        for (int m = 0; m < M; ++m)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int cc = 64 * m + l;
-                t[m][j] = (g < NG && cc < NB && cc <= r0 + j) ? T[cc + (size_t)(r0 + j) * NB] : (S)0;
-            }
+    static constexpr bool PAIR = NG > 8;
+    static_assert(NB % CH == 0 && NG <= 16, "register chain: n_b <= 256, chunks divide n_b");
+    LQ_DEV static constexpr int nch(int g) { return (16 * g + 16 + CH - 1) / CH; }
+    LQ_DEV static constexpr int n0of(int w) { return w < NG ? nch(w) : 0; }
+    LQ_DEV static constexpr int ntof(int w) { return n0of(w) + (PAIR ? nch(NG - 1 - w) : 0); }
+    static constexpr int maxn() {
+        int m = 0;
+        for (int w = 0; w < 8; ++w) m = ntof(w) > m ? ntof(w) : m;
+        return m;
     }
-    template <int M>
-    LQ_DEV static void apply_group(const S (&t)[M][16], int g, const double *u, int nq, double *out) {
-        const int l = lane_id(), r0 = 16 * g;
-        if (g >= NG) return;
-        for (int q = 0; q < nq; ++q) {
-            double v[16];
+    static constexpr int NCH = maxn();
+    V16<S> t[NCH][2];
+    LQ_DEV void load(const S *T) {
+        const int w = wave_id(), l = lane_id(), n0 = n0of(w), nt = ntof(w);
+        const __amdgpu_buffer_rsrc_t r = tile_rsrc(T, NB * NB * (int)sizeof(S));
+        const int voff = (VE * (l & 7) + (l >> 3) * NB) * (int)sizeof(S);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = 0.0;
+        for (int j = 0; j < NCH; ++j) {
+            const int g = j < n0 ? w : NG - 1 - w, m = j < n0 ? j : j - n0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int cc = 64 * m + l;
-                const double uc = cc < NB ? u[q * NB + cc] : 0.0;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) v[j] += (double)t[m][j] * uc;
-            }
-            const double tot = xreduce16(v);
-            if ((l & 3) == 0) out[q * NB + r0 + ((l >> 2) & 15)] = tot;
+            for (int h = 0; h < 2; ++h)
+                if (j < nt) t[j][h] = tile_load4(r, voff, (CH * m + (16 * g + 8 * h) * NB) * (int)sizeof(S));
         }
     }
-    LQ_DEV void load(const S *T) {
-        const int w = (int)(threadIdx.x >> 6);
-        load_group(t0, T, w);
-        if constexpr (TWO) load_group(t1, T, NG - 1 - w);
-    }
-    LQ_DEV void apply(const double *u, int nq, double *out) const {
-        const int w = (int)(threadIdx.x >> 6);
-        apply_group(t0, w, u, nq, out);
-        if constexpr (TWO) apply_group(t1, NG - 1 - w, u, nq, out);
+    LQ_DEV void apply(const double *u, int nq, double *out) {
+        const int w = wave_id(), l = lane_id(), n0 = n0of(w), nt = ntof(w);
+        for (int qq = 0; qq < nq; ++qq) {
+            // keeps the conversions to FP64 inside the loop over right-hand
+            // sides: hoisted out of it they would double the registers of T
+#pragma unroll
+            for (int j = 0; j < NCH; ++j)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) asm volatile("" : "+v"(t[j][h]));
+            double a[2][2] = {{0.0, 0.0}, {0.0, 0.0}};  // [group slot][h]
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                if (j >= nt) continue;  // uniform over the wave
+                const int g = j < n0 ? w : NG - 1 - w, m = j < n0 ? j : j - n0;
+                const int p0 = CH * m + VE * (l & 7);
+                double uv[VE];
+#pragma unroll
+                for (int e = 0; e < VE; ++e) uv[e] = u[qq * NB + p0 + e];
+                const bool diag = j == n0 - 1 || j == nt - 1;  // the chunk that reaches the diagonal
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int q = 16 * g + 8 * h + (l >> 3);
+                    double d = 0.0;
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) {
+                        double x = (double)t[j][h][e];
+                        if (diag) x = p0 + e <= q ? x : 0.0;  // T's strictly lower part is not held
+                        d += x * uv[e];
+                    }
+                    if (j < n0) a[0][h] += d;
+                    else a[1][h] += d;
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    double v = a[sl][h];
+                    v += xlane<5>(v);
+                    v += xlane<4>(v);
+                    v += xlane<3>(v);
+                    const bool has = sl == 0 ? n0 > 0 : PAIR;
+                    const int g = sl == 0 ? w : NG - 1 - w;
+                    if (has && (l & 7) == 0) out[qq * NB + 16 * g + 8 * h + (l >> 3)] = v;
+                }
+        }
     }
 };
 
 template <int NB, class S>
-static __global__ __launch_bounds__(chain_wg<S>()) void k_fwd_qr_chain(Ctx c, SolveArgs s, int k) {
-    constexpr int CHAIN_WG = chain_wg<S>();
+static __global__ __launch_bounds__((chain_wg<NB, S>())) void k_fwd_qr_chain(Ctx c, SolveArgs s, int k) {
+    constexpr int CHAIN_WG = chain_wg<NB, S>();
     if (c.dec[k] != 0 || gated(s.gate)) return;
     constexpr int RQ = rq<NB>(), NW = CHAIN_WG / 64;
     constexpr int PER = (NB * RQ + CHAIN_WG - 1) / CHAIN_WG;
@@ -308,10 +359,17 @@ static __global__ __launch_bounds__(chain_wg<S>()) void k_fwd_qr_chain(Ctx c, So
     __syncthreads();
     cols_dot<NB, NW, 1, S>(Tf + c.tqoff(k, k), u, nq, w, NB, 0, NB);  // w = T^T u
     __syncthreads();
-    for (int e = tid; e < NB * nq; e += CHAIN_WG) {  // z -= V w
+    for (int e = tid; e < NB * nq; e += CHAIN_WG) {  // z -= V w (V unit lower triangular)
         const int r = e % NB, q = e / NB;
+        const int rmax = min(NB - 1, r | 63);  // the wave's last row: the loop bound is uniform
         double acc = w[q * NB + r];
-        for (int cc = 0; cc < r; ++cc) acc += (double)V[r + (size_t)cc * NB] * w[q * NB + cc];
+        for (int c0 = 0; c0 < rmax; c0 += 32) {  // 32 loads in flight, then the sums in order
+            S v[32];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) v[j] = V[r + (size_t)(c0 + j) * NB];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) acc += (c0 + j < r ? (double)v[j] : 0.0) * w[q * NB + c0 + j];
+        }
         x[e] -= acc;
     }
     double gn[PER];  // g_i of the next tile row, loaded one iteration ahead
@@ -320,11 +378,16 @@ static __global__ __launch_bounds__(chain_wg<S>()) void k_fwd_qr_chain(Ctx c, So
         const int e = tid + p * CHAIN_WG;
         gn[p] = (k + 1 < c.n && e < NB * nq) ? s.G[gidx(k + 1, e)] : 0.0;
     }
-    constexpr bool REG = NB <= 256 && sizeof(S) == 4;  // T of the next tile prefetched into registers
-    ChainT<NB, S> tn;
-    if constexpr (REG)
-        if (k + 1 < c.n) tn.load(Tf + c.tqoff(k + 1, k));
-    for (int i = k + 1; i < c.n; ++i) {
+    // T of the next two tiles in registers (4-byte storage, n_b <= 256)
+    constexpr bool REG = NB <= 256 && sizeof(S) == 4;
+    constexpr int PD = REG ? 2 : 1;
+    ChainR<(REG ? NB : 32), float> ta, tb;
+    if constexpr (REG) {
+        if (k + 1 < c.n) ta.load((const float *)Tf + c.tqoff(k + 1, k));
+        if constexpr (PD == 2)
+            if (k + 2 < c.n) tb.load((const float *)Tf + c.tqoff(k + 2, k));
+    }
+    auto step = [&](int i, ChainR<(REG ? NB : 32), float> &tr) __attribute__((always_inline)) {
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int e = tid + p * CHAIN_WG;
@@ -337,8 +400,8 @@ static __global__ __launch_bounds__(chain_wg<S>()) void k_fwd_qr_chain(Ctx c, So
             gn[p] = (i + 1 < c.n && e < NB * nq) ? s.G[gidx(i + 1, e)] : 0.0;
         }
         if constexpr (REG) {
-            tn.apply(u, nq, w);
-            if (i + 1 < c.n) tn.load(Tf + c.tqoff(i + 1, k));
+            tr.apply(u, nq, w);
+            if (i + PD < c.n) tr.load((const float *)Tf + c.tqoff(i + PD, k));
         } else {
             cols_dot<NB, NW, 1, S>(Tf + c.tqoff(i, k), u, nq, w, NB, 0, NB);
         }
@@ -351,6 +414,11 @@ static __global__ __launch_bounds__(chain_wg<S>()) void k_fwd_qr_chain(Ctx c, So
                 s.G[gidx(i, e)] = w[e];
             }
         }
+    };
+    for (int i = k + 1; i < c.n; i += PD) {
+        step(i, ta);
+        if constexpr (PD == 2)
+            if (i + 1 < c.n) step(i + 1, tb);
     }
     for (int e = tid; e < NB * nq; e += CHAIN_WG) s.Z[gidx(k, e)] = x[e];
 }
@@ -360,6 +428,243 @@ template <int NB, class S>
 static __global__ __launch_bounds__(WG) void k_fwd_qr_u(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 0 || gated(s.gate)) return;
     tile_update<NB, S, 1>(c, s, k, k + 1, s.Y);
+}
+
+// ---------------------------------------------------------------------------
+// The forward pass as one wavefront launch (n_b = 256, 4-byte storage, no
+// diagonal domain).  Workgroup k replays step k on the right-hand sides tile
+// row by tile row, each as soon as step k-1 has finished with it, so the
+// steps overlap: a QR step's chain is sequential over its tile rows, but the
+// chains of different steps are not, and one step at a time left all but one
+// compute unit idle.  cnt[i] (one array per right-hand-side chunk) counts
+// the steps applied to y_i: workgroup k waits until cnt[i] >= k and sets it
+// to k+1 once y_i is updated (agent-scope release/acquire, as in the QR
+// step).  A workgroup waits only on lower-numbered ones, which are
+// dispatched first, so the launch completes whatever the residency.
+// A 256 x 256 column-major FP32 tile in registers over 512 threads: lane l
+// of wave w holds rows 4l..4l+3 of columns 32w..32w+31, one 16-byte load per
+// column, so a wave reads a whole column per instruction and all 32 loads
+// are in flight together.  Arithmetic in FP64, as in the per-step kernels.
+// ---------------------------------------------------------------------------
+constexpr int FW_WG = 512;
+constexpr int FW_RQ = 4;  // right-hand sides per workgroup
+
+struct FwTile {
+    f4 v[32];
+    LQ_DEV void load(const float *M) {
+        const int w = wave_id(), l = lane_id();
+        const __amdgpu_buffer_rsrc_t r = tile_rsrc(M, 256 * 256 * 4);
+        const int voff = (4 * l + 32 * w * 256) * 4;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = tile_load4(r, voff, j * 1024);
+    }
+    // keeps the conversions to FP64 inside the loop over right-hand sides
+    // (hoisted, they would double the registers of the tile)
+    LQ_DEV void pin() {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) asm volatile("" : "+v"(v[j]));
+    }
+};
+// entry (p, c) as used by MODE: 0 as stored; 1 upper triangle (p <= c);
+// 2 unit lower (below the diagonal as stored, 1 on it, 0 above)
+template <int MODE> LQ_DEV double fw_x(float m, int p, int c) {
+    if constexpr (MODE == 0) return (double)m;
+    else if constexpr (MODE == 1) return p <= c ? (double)m : 0.0;
+    else return p > c ? (double)m : (p == c ? 1.0 : 0.0);
+}
+// out[q*256 + c] = sum_p M(p, c) v[q*256 + p]   (v and out in LDS)
+template <int MODE> LQ_DEV void fw_cols(FwTile &t, const double *v, int nq, double *out) {
+    const int w = wave_id(), l = lane_id();
+    for (int q = 0; q < nq; ++q) {
+        t.pin();
+        double vv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vv[e] = v[q * 256 + 4 * l + e];
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb) {  // sixteen columns at a time (registers)
+            double s0[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                double a = 0.0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a += fw_x<MODE>(t.v[16 * hb + j][e], 4 * l + e, 32 * w + 16 * hb + j) * vv[e];
+                s0[j] = a;
+            }
+            const double a = xreduce16(s0);
+            if ((l & 3) == 0) out[q * 256 + 32 * w + 16 * hb + ((l >> 2) & 15)] = a;
+        }
+    }
+}
+// red[(w*nq + q)*256 + p] = sum over wave w's 32 columns of M(p, c) v[q*256 + c]
+template <int MODE> LQ_DEV void fw_rows(FwTile &t, const double *v, int nq, double *red) {
+    const int w = wave_id(), l = lane_id();
+    for (int q = 0; q < nq; ++q) {
+        t.pin();
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const double vc = v[q * 256 + 32 * w + j];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] += fw_x<MODE>(t.v[j][e], 4 * l + e, 32 * w + j) * vc;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[(w * nq + q) * 256 + 4 * l + e] = acc[e];
+    }
+}
+// The same row products for the FP64 unit-lower L_kk^{-1} (MODE 2), in four
+// passes of 8 columns per wave: lane l holds rows 2l, 2l+1 and 128+2l,
+// 128+2l+1.
+LQ_DEV void fw_rows_linv(const double *M, const double *v, int nq, double *red) {
+    const int w = wave_id(), l = lane_id();
+    double acc[FW_RQ][4];
+#pragma unroll
+    for (int q = 0; q < FW_RQ; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[q][e] = 0.0;
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+        d2 a[8][2];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                a[j][h] = *(const d2 *)(M + 128 * h + 2 * l + (size_t)(32 * w + 8 * pass + j) * 256);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int cc = 32 * w + 8 * pass + j;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int p = 128 * h + 2 * l + e;
+                    const double x = p > cc ? a[j][h][e] : (p == cc ? 1.0 : 0.0);
+#pragma unroll
+                    for (int q = 0; q < FW_RQ; ++q)
+                        if (q < nq) acc[q][2 * h + e] += x * v[q * 256 + cc];
+                }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < FW_RQ; ++q)
+        if (q < nq)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) red[(w * nq + q) * 256 + 128 * h + 2 * l + e] = acc[q][2 * h + e];
+}
+
+template <int NB, class S>
+static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, int *cnt) {
+    static_assert(NB == 256 && sizeof(S) == 4, "wavefront forward pass: n_b = 256, 4-byte storage");
+    if (gated(s.gate)) return;
+    __shared__ double yi[256 * FW_RQ], z[256 * FW_RQ], u[256 * FW_RQ];
+    __shared__ double red[8 * 256 * FW_RQ];
+    __shared__ int bail;
+    const int k = blockIdx.x, n = (int)c.n, tid = threadIdx.x;
+    const int q0 = blockIdx.y * FW_RQ, nq = min(FW_RQ, s.nrhs - q0);
+    int *cn = cnt + (size_t)blockIdx.y * n;
+    const int64_t Np = (int64_t)n * 256;
+    const float *At = (const float *)c.At, *Tf = (const float *)c.Tf;
+    auto gy = [&](int i, int e) { return (int64_t)i * 256 + e % 256 + (int64_t)(q0 + e / 256) * Np; };
+    auto wait = [&](int i) __attribute__((always_inline)) {
+        if (tid == 0) bail = !flag_wait(cn + i, k, &c.st->watchdog);
+        __syncthreads();
+        if (bail) return false;
+        fence_acquire();
+        return true;
+    };
+    auto publish = [&](int i) __attribute__((always_inline)) {
+        fence_release();
+        __syncthreads();
+        if (tid == 0) flag_publish(cn + i, k + 1);
+    };
+    // y_i -= (sum of the waves' row partials), then y_i is published
+    auto update_tile = [&](int i) __attribute__((always_inline)) {
+        __syncthreads();
+        for (int e = tid; e < 256 * nq; e += FW_WG) {
+            const int q = e / 256, p = e % 256;
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) t += red[(w * nq + q) * 256 + p];
+            s.Y[gy(i, e)] = yi[e] - t;
+        }
+        publish(i);
+    };
+    FwTile ty;
+    if (c.dec[k] == 1) {  // LU step: z_k = L_kk^{-1} P y_k, then y_i -= L_ik z_k
+        if (!wait(k)) return;
+        const int *pm = c.perm + (size_t)k * 256;
+        for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = s.Y[(int64_t)k * 256 + pm[e % 256] + (int64_t)(q0 + e / 256) * Np];
+        __syncthreads();
+        fw_rows_linv(c.Linv + (size_t)k * 256 * 256, yi, nq, red);
+        __syncthreads();
+        for (int e = tid; e < 256 * nq; e += FW_WG) {
+            const int q = e / 256, p = e % 256;
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) t += red[(w * nq + q) * 256 + p];
+            z[e] = t;
+            s.Z[gy(k, e)] = t;
+        }
+        if (k + 1 < n) ty.load(At + c.toff(k + 1, k));
+        for (int i = k + 1; i < n; ++i) {
+            if (!wait(i)) return;
+            for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = s.Y[gy(i, e)];
+            fw_rows<0>(ty, z, nq, red);
+            if (i + 1 < n) ty.load(At + c.toff(i + 1, k));
+            update_tile(i);
+        }
+        return;
+    }
+    // QR step: x = Q_kk^T y_k (GEQRT tile), then for i = k+1.. the flat tree:
+    // g = Y_ik^T y_i, w = T_ik^T (x + g), x -= w, y_i -= Y_ik w
+    ChainR<256, float> tc;
+    ty.load(At + c.toff(k, k));
+    if (!wait(k)) return;
+    for (int e = tid; e < 256 * nq; e += FW_WG) z[e] = s.Y[gy(k, e)];
+    __syncthreads();
+    fw_cols<2>(ty, z, nq, u);  // u = V^T x
+    tc.load(Tf + c.tqoff(k, k));
+    __syncthreads();
+    tc.apply(u, nq, yi);       // w = T^T u (yi as scratch)
+    ty.load(At + c.toff(k, k));
+    __syncthreads();
+    fw_rows<2>(ty, yi, nq, red);
+    __syncthreads();
+    for (int e = tid; e < 256 * nq; e += FW_WG) {
+        const int q = e / 256, p = e % 256;
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) t += red[(w * nq + q) * 256 + p];
+        z[e] -= t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+        // Y_ik is loaded before the wait, T_ik after g and Y_ik again after
+        // w (two tiles at once would exceed the registers)
+        ty.load(At + c.toff(i, k));
+        if (!wait(i)) return;  // (its barrier also orders the update of x above)
+        for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = s.Y[gy(i, e)];
+        __syncthreads();
+        fw_cols<0>(ty, yi, nq, u);  // g
+        tc.load(Tf + c.tqoff(i, k));
+        __syncthreads();
+        for (int e = tid; e < 256 * nq; e += FW_WG) u[e] += z[e];
+        __syncthreads();
+        double *wv = red + 7 * 256 * FW_RQ;  // w_i: the last wave's slot of red is free until fw_rows
+        tc.apply(u, nq, wv);
+        ty.load(At + c.toff(i, k));
+        __syncthreads();
+        for (int e = tid; e < 256 * nq; e += FW_WG) {
+            const double t = wv[e];
+            z[e] -= t;
+            u[e] = t;
+        }
+        __syncthreads();
+        fw_rows<0>(ty, u, nq, red);
+        update_tile(i);
+    }
+    __syncthreads();
+    for (int e = tid; e < 256 * nq; e += FW_WG) s.Z[gy(k, e)] = z[e];
 }
 
 // Back-substitution, part 1: x_k = D_k^{-1} z_k (D_k = U or R of step k;
