@@ -58,7 +58,9 @@ template <> struct Tr<PB16> {
 template <class A> LQ_DEV A zero_acc() { A z; for (int r = 0; r < 4; ++r) z[r] = 0; return z; }
 
 LQ_DEV int lane_id() { return threadIdx.x & 63; }
-LQ_DEV int wave_id() { return threadIdx.x >> 6; }
+// uniform over the wave: readfirstlane lets the compiler keep wave-dependent
+// values (offsets, loop bounds) in scalar registers
+LQ_DEV int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 // ---- lane exchanges and wave reductions (64 lanes) ---------------------------
 // Six partner maps whose composition reaches every lane: xor 32 and xor 16

@@ -438,9 +438,12 @@ static __global__ __launch_bounds__(WG) void k_fwd_qr_u(Ctx c, SolveArgs s, int 
 // chains of different steps are not, and one step at a time left all but one
 // compute unit idle.  cnt[i] (one array per right-hand-side chunk) counts
 // the steps applied to y_i: workgroup k waits until cnt[i] >= k and sets it
-// to k+1 once y_i is updated (agent-scope release/acquire, as in the QR
-// step).  A workgroup waits only on lower-numbered ones, which are
-// dispatched first, so the launch completes whatever the residency.
+// to k+1 once y_i is updated.  y is written and read with agent-scope
+// atomic stores and loads (coherent across the chip's L2 caches), the
+// writer waits for its stores to complete before the counter is set, so no
+// cache writeback or invalidation is needed for the handoff.  A workgroup
+// waits only on lower-numbered ones, which are dispatched first, so the
+// launch completes whatever the residency.
 // A 256 x 256 column-major FP32 tile in registers over 512 threads: lane l
 // of wave w holds rows 4l..4l+3 of columns 32w..32w+31, one 16-byte load per
 // column, so a wave reads a whole column per instruction and all 32 loads
@@ -456,7 +459,7 @@ struct FwTile {
         const __amdgpu_buffer_rsrc_t r = tile_rsrc(M, 256 * 256 * 4);
         const int voff = (4 * l + 32 * w * 256) * 4;
 #pragma unroll
-        for (int j = 0; j < 32; ++j) v[j] = tile_load4(r, voff, j * 1024);
+        for (int j = 0; j < 32; ++j) v[j] = tile_load4(r, voff + (j & 3) * 1024, (j >> 2) * 4096);  // imm + 8 scalars
     }
     // keeps the conversions to FP64 inside the loop over right-hand sides
     // (hoisted, they would double the registers of the tile)
@@ -566,17 +569,28 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
     const int64_t Np = (int64_t)n * 256;
     const float *At = (const float *)c.At, *Tf = (const float *)c.Tf;
     auto gy = [&](int i, int e) { return (int64_t)i * 256 + e % 256 + (int64_t)(q0 + e / 256) * Np; };
+    auto ld = [&](int64_t idx) { return __hip_atomic_load(s.Y + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
     auto wait = [&](int i) __attribute__((always_inline)) {
-        if (tid == 0) bail = !flag_wait(cn + i, k, &c.st->watchdog);
+        if (tid == 0) {
+            long spins = 0;
+            bail = 0;
+            while (__hip_atomic_load(cn + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1L << 27) ||
+                    __hip_atomic_load(&c.st->watchdog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(&c.st->watchdog, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bail = 1;
+                    break;
+                }
+            }
+        }
         __syncthreads();
-        if (bail) return false;
-        fence_acquire();
-        return true;
+        return !bail;
     };
     auto publish = [&](int i) __attribute__((always_inline)) {
-        fence_release();
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's stores of y_i have completed
         __syncthreads();
-        if (tid == 0) flag_publish(cn + i, k + 1);
+        if (tid == 0) __hip_atomic_store(cn + i, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     // y_i -= (sum of the waves' row partials), then y_i is published
     auto update_tile = [&](int i) __attribute__((always_inline)) {
@@ -586,7 +600,7 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
             double t = 0.0;
 #pragma unroll
             for (int w = 0; w < 8; ++w) t += red[(w * nq + q) * 256 + p];
-            s.Y[gy(i, e)] = yi[e] - t;
+            __hip_atomic_store(s.Y + gy(i, e), yi[e] - t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         publish(i);
     };
@@ -594,7 +608,7 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
     if (c.dec[k] == 1) {  // LU step: z_k = L_kk^{-1} P y_k, then y_i -= L_ik z_k
         if (!wait(k)) return;
         const int *pm = c.perm + (size_t)k * 256;
-        for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = s.Y[(int64_t)k * 256 + pm[e % 256] + (int64_t)(q0 + e / 256) * Np];
+        for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = ld((int64_t)k * 256 + pm[e % 256] + (int64_t)(q0 + e / 256) * Np);
         __syncthreads();
         fw_rows_linv(c.Linv + (size_t)k * 256 * 256, yi, nq, red);
         __syncthreads();
@@ -609,7 +623,7 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
         if (k + 1 < n) ty.load(At + c.toff(k + 1, k));
         for (int i = k + 1; i < n; ++i) {
             if (!wait(i)) return;
-            for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = s.Y[gy(i, e)];
+            for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = ld(gy(i, e));
             fw_rows<0>(ty, z, nq, red);
             if (i + 1 < n) ty.load(At + c.toff(i + 1, k));
             update_tile(i);
@@ -621,7 +635,7 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
     ChainR<256, float> tc;
     ty.load(At + c.toff(k, k));
     if (!wait(k)) return;
-    for (int e = tid; e < 256 * nq; e += FW_WG) z[e] = s.Y[gy(k, e)];
+    for (int e = tid; e < 256 * nq; e += FW_WG) z[e] = ld(gy(k, e));
     __syncthreads();
     fw_cols<2>(ty, z, nq, u);  // u = V^T x
     tc.load(Tf + c.tqoff(k, k));
@@ -639,14 +653,14 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
         z[e] -= t;
     }
     for (int i = k + 1; i < n; ++i) {
-        // Y_ik is loaded before the wait, T_ik after g and Y_ik again after
-        // w (two tiles at once would exceed the registers)
+        // Y_ik is loaded before the wait, T_ik after it and Y_ik again after
+        // w (holding Y_ik through w as well would exceed the registers)
         ty.load(At + c.toff(i, k));
         if (!wait(i)) return;  // (its barrier also orders the update of x above)
-        for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = s.Y[gy(i, e)];
+        tc.load(Tf + c.tqoff(i, k));
+        for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = ld(gy(i, e));
         __syncthreads();
         fw_cols<0>(ty, yi, nq, u);  // g
-        tc.load(Tf + c.tqoff(i, k));
         __syncthreads();
         for (int e = tid; e < 256 * nq; e += FW_WG) u[e] += z[e];
         __syncthreads();
