@@ -216,6 +216,96 @@ double oracle_inv_norm1(int64_t m, const double *LU, int64_t ldw, const int32_t 
     return best;
 }
 
+/* Products with B = U^{-1} L^{-1} (the inverse of P W up to the column
+ * permutation, which leaves the 1-norm unchanged) and with B^T, from the
+ * factors L\U in place: triangular solves in the plain loop order.        */
+static void est_apply(int64_t m, const double *LU, int64_t ldw, double *x, int transpose)
+{
+    if (!transpose) {
+        for (int64_t c = 0; c < m; ++c) /* L t = x (unit lower) */
+            for (int64_t r = c + 1; r < m; ++r) x[r] -= LU[IX(r, c, ldw)] * x[c];
+        for (int64_t c = m - 1; c >= 0; --c) { /* U y = t */
+            x[c] /= LU[IX(c, c, ldw)];
+            for (int64_t r = 0; r < c; ++r) x[r] -= LU[IX(r, c, ldw)] * x[c];
+        }
+    } else {
+        for (int64_t r = 0; r < m; ++r) { /* U^T t = x */
+            double v = x[r];
+            for (int64_t c = 0; c < r; ++c) v -= LU[IX(c, r, ldw)] * x[c];
+            x[r] = v / LU[IX(r, r, ldw)];
+        }
+        for (int64_t r = m - 1; r >= 0; --r) { /* L^T z = t (unit lower) */
+            double v = x[r];
+            for (int64_t c = r + 1; c < m; ++c) v -= LU[IX(c, r, ldw)] * x[c];
+            x[r] = v;
+        }
+    }
+}
+
+static double est_norm1(int64_t m, const double *x)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i) s += fabs(x[i]);
+    return s;
+}
+
+static int64_t est_argmax(int64_t m, const double *x) /* first index of the largest |x_i| */
+{
+    int64_t j = 0;
+    for (int64_t i = 1; i < m; ++i)
+        if (fabs(x[i]) > fabs(x[j])) j = i;
+    return j;
+}
+
+/* Estimate of ||W^{-1}||_1 in O(m^2) per iteration from the factors P W = L U
+ * (Sec. 3.4: the inverse norm costs a few triangular solves when estimated):
+ * Hager's method with Higham's refinements, the iteration LAPACK runs for its
+ * condition estimates.  With B = W^{-1}:
+ *   x = (1/m, ..., 1/m); y = B x; est = ||y||_1; xi = sign(y); z = B^T xi;
+ *   up to four times: j = the first index of max |z|, y = B e_j,
+ *   est = ||y||_1; stop if sign(y) repeats xi or est did not grow (the new
+ *   value stands, as in Higham's algorithm); else xi = sign(y), z = B^T xi,
+ *   and stop when the previous j already attains it (z_jlast == ||z||_inf);
+ *   finally x_i = (-1)^i (1 + i/(m-1)), est = max(est, 2 ||B x||_1 / (3m)).
+ * sign(0) = +1.  The result is a lower bound of ||W^{-1}||_1 (every est is
+ * ||B x||_1 for some ||x||_1 <= 1).                                        */
+double oracle_inv_norm1_est(int64_t m, const double *LU, int64_t ldw)
+{
+    double *x = (double *)malloc((size_t)m * sizeof(double));
+    int *xi = (int *)malloc((size_t)m * sizeof(int));
+    for (int64_t i = 0; i < m; ++i) x[i] = 1.0 / (double)m;
+    est_apply(m, LU, ldw, x, 0);
+    double est = est_norm1(m, x);
+    if (m > 1) {
+        for (int64_t i = 0; i < m; ++i) { xi[i] = x[i] >= 0.0 ? 1 : -1; x[i] = (double)xi[i]; }
+        est_apply(m, LU, ldw, x, 1);
+        int64_t j = est_argmax(m, x);
+        int iter = 2;
+        for (;;) {
+            for (int64_t i = 0; i < m; ++i) x[i] = (i == j) ? 1.0 : 0.0;
+            est_apply(m, LU, ldw, x, 0);
+            const double estold = est;
+            est = est_norm1(m, x);
+            int same = 1;
+            for (int64_t i = 0; i < m; ++i) same &= ((x[i] >= 0.0 ? 1 : -1) == xi[i]);
+            if (same) break;               /* repeated sign vector: converged */
+            if (est <= estold) break;      /* no growth: cycling (the new value stands) */
+            for (int64_t i = 0; i < m; ++i) { xi[i] = x[i] >= 0.0 ? 1 : -1; x[i] = (double)xi[i]; }
+            est_apply(m, LU, ldw, x, 1);
+            const int64_t jlast = j;
+            j = est_argmax(m, x);
+            if (x[jlast] == fabs(x[j]) || iter >= 5) break;
+            ++iter;
+        }
+        for (int64_t i = 0; i < m; ++i) x[i] = (i % 2 ? -1.0 : 1.0) * (1.0 + (double)i / (double)(m - 1));
+        est_apply(m, LU, ldw, x, 0);
+        const double alt = 2.0 * est_norm1(m, x) / (3.0 * (double)m);
+        if (alt > est) est = alt;
+    }
+    free(x); free(xi);
+    return est;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Householder reflector (Golub & Van Loan, Sec. 5.1, with the LAPACK sign  */
 /* convention): given alpha and the tail x of length len, find beta, tau,  */
@@ -422,11 +512,11 @@ static double step_units(int64_t r, int is_qr)
 /*                    them to the trailing columns of the domain's rows and */
 /*                    stores the domain's multipliers, and ipiv[k*nb + c]   */
 /*                    holds the stacked row exchanged at column c.          */
-int oracle_factor_domain(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
-                         uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
-                         double *B, int64_t ldb, int64_t nrhs,
-                         int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
-                         double *margin_out, double *diag, int32_t domain_stride)
+int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
+                     uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
+                     double *B, int64_t ldb, int64_t nrhs,
+                     int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
+                     double *margin_out, double *diag, int32_t domain_stride, int32_t invnorm_estimate)
 {
     if (N < 1) return -1;
     if (nb < 1) return -4;
@@ -518,7 +608,8 @@ int oracle_factor_domain(int64_t N, double *A, int64_t lda, int64_t nb, int32_t 
         double s = 0.0, m = 0.0;
         int nonfinite = 0;
         if (!zero_piv) {
-            double inv = oracle_inv_norm1(mk, W, nb, piv);
+            /* ||A_kk^{-1}||_1 exactly, or its O(n_b^2) estimate (Sec. 3.4) */
+            double inv = invnorm_estimate ? oracle_inv_norm1_est(mk, W, nb) : oracle_inv_norm1(mk, W, nb, piv);
             s = 1.0 / inv;
         }
         for (int64_t j = 0; j < mk; ++j) away[j] = 0.0;
@@ -689,6 +780,16 @@ int oracle_factor_domain(int64_t N, double *A, int64_t lda, int64_t nb, int32_t 
     free(piv); free(W); free(Tloc); free(colsum_scratch); free(away); free(lmax); free(nrm_before);
     free(dtile); free(Wd); free(Pd); free(dpiv);
     return 0;
+}
+
+int oracle_factor_domain(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
+                         uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
+                         double *B, int64_t ldb, int64_t nrhs,
+                         int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
+                         double *margin_out, double *diag, int32_t domain_stride)
+{
+    return oracle_factor_ex(N, A, lda, nb, criterion, alpha, seed, forced, mumps_reading, nsteps, B, ldb, nrhs,
+                            ipiv, Tq, dec, s_out, m_out, margin_out, diag, domain_stride, 0);
 }
 
 int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,

@@ -58,6 +58,11 @@ def lib():
         L.oracle_factor_domain.restype = C.c_int
         L.oracle_factor_domain.argtypes = [i64, dp, i64, i64, i32, f64, C.c_uint64, bp, i32, i64,
                                            dp, i64, i64, ip, dp, bp, dp, dp, dp, dp, i32]
+        L.oracle_factor_ex.restype = C.c_int
+        L.oracle_factor_ex.argtypes = [i64, dp, i64, i64, i32, f64, C.c_uint64, bp, i32, i64,
+                                       dp, i64, i64, ip, dp, bp, dp, dp, dp, dp, i32, i32]
+        L.oracle_inv_norm1_est.restype = f64
+        L.oracle_inv_norm1_est.argtypes = [i64, dp, i64]
         L.oracle_solve.restype = None
         L.oracle_solve.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64]
         L.oracle_solve_domain.restype = None
@@ -135,10 +140,12 @@ class OracleFactors:
 
 
 def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading=0,
-           nsteps=-1, B=None, domain=0) -> OracleFactors:
+           nsteps=-1, B=None, domain=0, estimate=False) -> OracleFactors:
     """Hybrid LU-QR factorization (Alg. 1) of a copy of A.  domain = p > 0
     pivots the LU attempt over the diagonal domain (the panel tiles k, k+p,
-    k+2p, ...; Sec. 2.1), domain = 0 within the diagonal tile."""
+    k+2p, ...; Sec. 2.1), domain = 0 within the diagonal tile.  estimate:
+    the criteria take ||A_kk^{-1}||_1 from the O(n_b^2) iterative estimate
+    (Sec. 3.4) instead of computing it exactly."""
     A = _fortran(A)
     N = A.shape[0]
     assert A.shape == (N, N)
@@ -160,7 +167,11 @@ def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading
     if B is not None:
         Bt = _fortran(B.reshape(N, -1) if B.ndim == 1 else B)
         nrhs = Bt.shape[1]
-    if domain:
+    if estimate:
+        rc = lib().oracle_factor_ex(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
+                                    int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
+                                    _b(dec), _d(s), _d(m), _d(margin), _d(diag), int(domain), 1)
+    elif domain:
         rc = lib().oracle_factor_domain(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
                                         int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
                                         _b(dec), _d(s), _d(m), _d(margin), _d(diag), int(domain))
@@ -214,6 +225,13 @@ def inv_norm1(LU, ipiv):
     LU = _fortran(LU)
     ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
     return lib().oracle_inv_norm1(LU.shape[0], _d(LU), LU.shape[0], _i(ipiv))
+
+
+def inv_norm1_est(LU):
+    """O(m^2)-per-iteration estimate of ||W^{-1}||_1 from the factors L\\U of P W
+    (Sec. 3.4; the permutation does not change the 1-norm)."""
+    LU = _fortran(LU)
+    return lib().oracle_inv_norm1_est(LU.shape[0], _d(LU), LU.shape[0])
 
 
 def tile_norm1(A):
