@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--criterion", default="max")
     ap.add_argument("--alpha", type=float, default=None,
                     help="threshold of the criterion (default 5e4 for the single system, 1 for the batched workload)")
+    ap.add_argument("--alpha-growth", type=float, default=None, metavar="G",
+                    help="take alpha from a tile-norm growth budget G (luqr_alpha_for_growth: the bound of Sec. "
+                         "3.1 for Max, Sec. 3.2 for Sum) instead of --alpha")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16", "fp64"))
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--max-iter", type=int, default=10)
@@ -68,6 +71,8 @@ def parse():
     ap.add_argument("--input-cache", default="", metavar="PATH",
                     help="raw FP64 file of A: loaded if it exists, else written after generation (lets "
                          "profiled runs skip the factorizations that build U and V)")
+    ap.add_argument("--estimate", action="store_true",
+                    help="take ||A_kk^-1||_1 from the O(n_b^2) iterative estimate (Sec. 3.4) instead of exactly")
     ap.add_argument("--dump-steps", default="", metavar="PATH",
                     help="write the per-step phase durations (mean over the timed steps), decisions and margins "
                          "of the timed path to PATH as JSON")
@@ -75,6 +80,9 @@ def parse():
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (the reference kernel "
                          "for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.alpha_growth is not None:
+        from paper_1401_5522_amd import _lib
+        args.alpha = _lib.luqr_alpha_for_growth(args.N, args.nb, args.criterion, args.alpha_growth)
     if args.alpha is None:
         args.alpha = 1.0 if args.workload == "batched" else 5e4
     return args
@@ -420,7 +428,7 @@ def main():
     B = torch.from_numpy(np.asfortranarray(inputs.rhs(N, args.nrhs, seed=(args.seed,)).reshape(N, -1))).cuda()
     B = B.t().contiguous().t()
     torch.cuda.synchronize()
-    kw = dict(criterion=args.criterion, alpha=args.alpha, seed=args.seed, nrhs_max=args.nrhs)
+    kw = dict(criterion=args.criterion, alpha=args.alpha, seed=args.seed, nrhs_max=args.nrhs, estimate=args.estimate)
 
     nb64 = min(nb, 256)  # the FP64 path stops at n_b = 256
 
@@ -516,7 +524,8 @@ def main():
                                f"{prec}+fp64-{'GMRES-IR' if args.refine == 'gmres' else 'IR'} nrhs={args.nrhs}",
                    "N": N, "nb": nb, "nrhs": args.nrhs, "kappa": args.kappa, "criterion": args.criterion,
                    "refine": args.refine,
-                   "alpha": args.alpha, "precision": prec, "parallelism": "single GPU"},
+                   "alpha": args.alpha, "precision": prec, "parallelism": "single GPU",
+                   "inverse_norm": "estimate" if args.estimate else "exact"},
         "solves_per_s": round(1e3 / ms, 4),
         "eta": eta,
         "eta_target": N * 1e-16,

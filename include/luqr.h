@@ -91,6 +91,15 @@ typedef struct {
                             indices.  Supported while the first step's domain has at most
                             512 rows ((1 + (n-1)/p) nb <= 512), else LUQR_ERR_UNSUPPORTED;
                             not by the batched entry points. */
+    int32_t invnorm_estimate; /* 0 (default): the Max and Sum criteria take ||A_kk^-1||_1
+                            exactly (the product U^-1 L^-1 of the explicit FP64 inverses).
+                            1: from the O(n_b^2)-per-iteration estimate of Sec. 3.4 (Hager's
+                            iteration with Higham's refinements, as in LAPACK's condition
+                            estimator; at most five products with A_kk^-1 and four with
+                            its transpose, each through the explicit inverses).  The
+                            estimate is a lower bound, so s_k = 1/est can only be larger
+                            than the exact one: an LU step of the exact criterion stays
+                            LU.  Not by the batched entry points. */
 } luqr_opts;
 
 /* Device-side numerical status, read back by luqr_get_status. */
@@ -161,6 +170,20 @@ int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda, int64_t nr
 int luqr_solve_gmres_ir(luqr_factors f, const double *dA, int64_t lda, const double *db,
                         double *dx, int32_t max_outer, int32_t max_inner,
                         int32_t *inner_total, void *stream);
+
+/* alpha from a growth budget, for the Max and Sum criteria (the choice of alpha
+ * is left open in Sec. 5.2 and Sec. 7; this takes it from the bounds of Sec. 3):
+ * the largest alpha whose worst-case growth of the tile norms,
+ * max_{i,j,k} ||A_ij^(k)||_1 / max_{i,j} ||A_ij||_1, stays within `growth`
+ * for an N x N matrix in n = ceil(N/nb) tiles.
+ *   Max (Sec. 3.1): growth <= (1 + alpha)^(n-1), so alpha = growth^(1/(n-1)) - 1.
+ *   Sum (Sec. 3.2): the column sums of tile norms grow by at most max(1, alpha)
+ *     per step, so growth <= n max(1, alpha)^(n-1): alpha = (growth/n)^(1/(n-1))
+ *     for growth >= n, and 0 (every step QR) below n, which no alpha > 0 meets.
+ *   One tile (n = 1): +inf (the step is the tile's own GEPP).
+ * Host arithmetic only.  Returns alpha >= 0, or -1 (N < 1 or nb < 1), -3 (a
+ * criterion other than Max or Sum), -4 (growth < 1 or NaN). */
+double luqr_alpha_for_growth(int64_t N, int32_t nb, int32_t criterion, double growth);
 
 /* Copy the decision sequence (1 = LU, 0 = QR), s_k = 1/||A_kk^-1||_1, m_k (the
  * max or sum of sub-diagonal tile norms) and the relative margin

@@ -20,7 +20,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTED = ["luqr_workspace_bytes", "luqr_factor", "luqr_solve", "luqr_solve_refined", "luqr_solve_gmres_ir",
             "luqr_get_decisions", "luqr_get_status", "luqr_get_step_times", "luqr_export_factors", "luqr_destroy",
-            "luqr_solve_noalloc",
+            "luqr_solve_noalloc", "luqr_alpha_for_growth",
             "luqr_batched_workspace_bytes", "luqr_batched_plan", "luqr_batched_run", "luqr_batched_decision_stride",
             "luqr_batched_destroy", "luqr_batched_autotune"]
 
@@ -29,7 +29,8 @@ class luqr_opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("criterion", C.c_int32), ("alpha", C.c_double),
                 ("precision", C.c_int32), ("nrhs_max", C.c_int32), ("seed", C.c_uint64),
                 ("forced", C.POINTER(C.c_int8)), ("nsteps", C.c_int32),
-                ("timing", C.c_int32), ("no_lookahead", C.c_int32), ("domain_stride", C.c_int32)]
+                ("timing", C.c_int32), ("no_lookahead", C.c_int32), ("domain_stride", C.c_int32),
+                ("invnorm_estimate", C.c_int32)]
 
 
 class luqr_status(C.Structure):
@@ -77,6 +78,8 @@ def lib() -> C.CDLL:
     L.luqr_solve_refined.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, i32, vp]
     L.luqr_solve_gmres_ir.restype = C.c_int
     L.luqr_solve_gmres_ir.argtypes = [vp, vp, i64, vp, vp, i32, i32, C.POINTER(C.c_int32), vp]
+    L.luqr_alpha_for_growth.restype = C.c_double
+    L.luqr_alpha_for_growth.argtypes = [i64, i32, i32, C.c_double]
     L.luqr_get_decisions.restype = C.c_int
     L.luqr_get_decisions.argtypes = [vp, vp, vp, vp, vp, i64]
     L.luqr_get_status.restype = C.c_int
@@ -106,7 +109,7 @@ def lib() -> C.CDLL:
 
 
 def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed=0, forced=None,
-              nsteps=-1, timing=False, lookahead=True, domain=0):
+              nsteps=-1, timing=False, lookahead=True, domain=0, estimate=False):
     o = luqr_opts()
     o.nb = int(nb)
     o.criterion = CRITERIA[criterion] if isinstance(criterion, str) else int(criterion)
@@ -122,6 +125,7 @@ def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed
     o.timing = 1 if timing else 0
     o.no_lookahead = 0 if lookahead else 1
     o.domain_stride = int(domain)
+    o.invnorm_estimate = 1 if estimate else 0
     return o, keep
 
 
@@ -151,6 +155,14 @@ def luqr_solve_gmres_ir(h, dA, lda, db, dx, max_outer, max_inner, stream):
     check(lib().luqr_solve_gmres_ir(h, dA, lda, db, dx, max_outer, max_inner, C.byref(inner), stream),
           "luqr_solve_gmres_ir")
     return inner.value
+
+
+def luqr_alpha_for_growth(N, nb, criterion, growth):
+    crit = CRITERIA[criterion] if isinstance(criterion, str) else int(criterion)
+    a = lib().luqr_alpha_for_growth(int(N), int(nb), crit, float(growth))
+    if a < 0:
+        raise LuqrError(f"luqr_alpha_for_growth: invalid argument {int(-a)}")
+    return a
 
 
 def luqr_get_decisions(h, dec, s, m, margin, n):

@@ -1,5 +1,6 @@
 // C ABI of the hybrid LU-QR solver (declarations and contracts in luqr.h).
 #include <math.h>
+#include <cmath>
 #include <string.h>
 
 #include <mutex>
@@ -62,6 +63,7 @@ static int check_opts(int64_t N, const luqr_opts *o, int pos_opts) {
     if (o->precision < 0 || o->precision > 2) return -pos_opts;
     if (o->criterion == LUQR_CRIT_FORCED && !o->forced) return -pos_opts;
     if (o->domain_stride < 0) return -pos_opts;
+    if (o->invnorm_estimate < 0 || o->invnorm_estimate > 1) return -pos_opts;
     if (!pick_ops(o->nb, o->precision)) return LUQR_ERR_UNSUPPORTED;
     if (o->domain_stride > 0) {  // the domain's GEPP holds at most 512 stacked rows in one workgroup
         const int64_t n = (N + o->nb - 1) / o->nb;
@@ -362,6 +364,18 @@ extern "C" int luqr_solve_gmres_ir(luqr_factors f, const double *dA, int64_t lda
     if (inner_total) *inner_total = inner;
     k_rhs_out<<<nblk(N), WG, 0, st>>>(X, dx, N, N, Np, 1);
     return hip_rc(hipGetLastError());
+}
+
+extern "C" double luqr_alpha_for_growth(int64_t N, int32_t nb, int32_t criterion, double growth) {
+    if (N < 1 || nb < 1) return -1.0;
+    if (criterion != LUQR_CRIT_MAX && criterion != LUQR_CRIT_SUM) return -3.0;
+    if (!(growth >= 1.0)) return -4.0;
+    const int64_t n = (N + nb - 1) / nb;
+    if (n == 1) return INFINITY;
+    const double e = 1.0 / (double)(n - 1);
+    if (criterion == LUQR_CRIT_MAX) return std::pow(growth, e) - 1.0;  // (1 + alpha)^(n-1) = growth
+    if (growth < (double)n) return 0.0;                                // the Sum bound is n at best
+    return std::pow(growth / (double)n, e);                            // n alpha^(n-1) = growth
 }
 
 extern "C" int luqr_get_decisions(luqr_factors f, int8_t *dec, double *s, double *m, double *margin, int64_t n) {

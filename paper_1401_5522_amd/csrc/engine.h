@@ -8,6 +8,7 @@
 #include "panel.h"
 #include "qr.h"
 #include "solve.h"
+#include "est.h"
 
 namespace lq {
 
@@ -62,7 +63,8 @@ struct Eng {
                 k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);
             }
             k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
-            k_panel_invnorm<NB><<<(NB / B) * (NB / B), WG, 0, st>>>(c, k);
+            if (o.invnorm_estimate) k_panel_invest<NB><<<1, WG, 0, st>>>(c, k);
+            else k_panel_invnorm<NB><<<(NB / B) * (NB / B), WG, 0, st>>>(c, k);
             DecideArgs a;
             a.crit = o.criterion;
             a.alpha = o.alpha;

@@ -29,7 +29,8 @@ def test_library_exports_every_symbol():
 
 def test_struct_layouts_match_header():
     from paper_1401_5522_amd import _lib
-    assert C.sizeof(_lib.luqr_opts) == 56
+    assert C.sizeof(_lib.luqr_opts) == 64
+    assert _lib.luqr_opts.invnorm_estimate.offset == 56
     assert _lib.luqr_opts.forced.offset == 32
     assert C.sizeof(_lib.luqr_status) == 40
     assert _lib.luqr_status.ir_eta.offset == 24
