@@ -22,6 +22,10 @@
  *              U_kj = L_kk^{-1} P_kk A_kj to its right (Alg. 2).
  *     QR step: V\R of the diagonal tile (unit lower V), the TS reflector
  *              tails Y_ik below it, Q^T A_kj to its right (Alg. 3/4a).
+ *     LU step, variant A2 (lu_variant = 2, Sec. 2.3): V\U of the GEQRT of
+ *              the diagonal tile, L_ik = A_ik U_kk^{-1} below it,
+ *              U_kj = Q_kk^T A_kj to its right; ipiv is the identity and
+ *              Tq(k,k) holds the GEQRT factor.
  *   Tq     n*n blocks of nb*nb: block (i,k) at Tq + (k*n + i)*nb*nb holds the
  *          upper-triangular compact-WY factor of the reflectors that
  *          eliminated tile (i,k) (TSQRT), or of GEQRT for i == k.
@@ -306,6 +310,35 @@ double oracle_inv_norm1_est(int64_t m, const double *LU, int64_t ldw)
     return est;
 }
 
+/* ||A^{-1}||_1 of an m x m tile from its GEQRT factors (variant A2, Sec.
+ * 2.3: A = Q U with Q given by the unit-lower reflectors V and the compact-WY
+ * factor T, U upper triangular).  By definition A^{-1} = U^{-1} Q^T: Q^T is
+ * formed by applying the reflectors to the identity, then every column is
+ * back-substituted with U, and the largest absolute column sum is returned.
+ * VR holds V below the diagonal and U on and above it; U must have no zero
+ * on its diagonal. */
+void oracle_unmqr(int64_t mk, const double *V, int64_t ldv, const double *T, int64_t ldt,
+                  int64_t nc, double *C, int64_t ldc);
+double oracle_inv_norm1_qr(int64_t m, const double *VR, int64_t ldv, const double *T, int64_t ldt)
+{
+    double *X = (double *)calloc((size_t)(m > 0 ? m * m : 1), sizeof(double));
+    for (int64_t i = 0; i < m; ++i) X[IX(i, i, m)] = 1.0;
+    oracle_unmqr(m, VR, ldv, T, ldt, m, X, m);
+    double best = 0.0;
+    for (int64_t j = 0; j < m; ++j) {
+        for (int64_t c = m - 1; c >= 0; --c) {
+            const double x = X[IX(c, j, m)] / VR[IX(c, c, ldv)];
+            X[IX(c, j, m)] = x;
+            for (int64_t r = 0; r < c; ++r) X[IX(r, j, m)] -= VR[IX(r, c, ldv)] * x;
+        }
+        double sum = 0.0;
+        for (int64_t i = 0; i < m; ++i) sum += fabs(X[IX(i, j, m)]);
+        if (sum > best || isnan(sum)) best = sum;
+    }
+    free(X);
+    return best;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Householder reflector (Golub & Van Loan, Sec. 5.1, with the LAPACK sign  */
 /* convention): given alpha and the tail x of length len, find beta, tau,  */
@@ -485,12 +518,16 @@ static void gemm_minus(int64_t mi, int64_t nc, int64_t mk, const double *A, int6
         }
 }
 
-/* Table 1 work of step k with r = n-k-1 trailing tiles, in units of nb^3. */
-static double step_units(int64_t r, int is_qr)
+/* Table 1 work of step k with r = n-k-1 trailing tiles, in units of nb^3.
+ * Variant A2 (Sec. 2.3) doubles the Factor (GEQRT instead of GETRF) and the
+ * Apply (ORMQR instead of TRSM) of an LU step: 4/3 + 3r + 2r^2. */
+static double step_units_v(int64_t r, int is_qr, int a2)
 {
     double u = 2.0 / 3.0 + 2.0 * (double)r + 2.0 * (double)r * (double)r;
-    return is_qr ? 2.0 * u : u;
+    if (is_qr) return 2.0 * u;
+    return a2 ? u + 2.0 / 3.0 + (double)r : u;
 }
+static double step_units(int64_t r, int is_qr) { return step_units_v(r, is_qr, 0); }
 
 /* ---------------------------------------------------------------------- */
 /* The hybrid LU-QR factorization (Alg. 1).                                */
@@ -512,11 +549,20 @@ static double step_units(int64_t r, int is_qr)
 /*                    them to the trailing columns of the domain's rows and */
 /*                    stores the domain's multipliers, and ipiv[k*nb + c]   */
 /*                    holds the stacked row exchanged at column c.          */
+/*   lu_variant       0 or 1: LU steps of variant A1 (Alg. 2, GEPP on a     */
+/*                    backup copy); 2: variant A2 (Sec. 2.3): every step    */
+/*                    starts with GEQRT of A_kk in place, the criterion     */
+/*                    takes ||A_kk^{-1}||_1 from those factors, an LU step  */
+/*                    eliminates with U = R and applies Q^T, and a QR step  */
+/*                    continues from the same GEQRT.  A2 is defined for the */
+/*                    Max, Sum, Random and Forced criteria without a domain */
+/*                    or the estimate (-23 otherwise).                      */
 int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
                      uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
                      double *B, int64_t ldb, int64_t nrhs,
                      int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
-                     double *margin_out, double *diag, int32_t domain_stride, int32_t invnorm_estimate)
+                     double *margin_out, double *diag, int32_t domain_stride, int32_t invnorm_estimate,
+                     int32_t lu_variant)
 {
     if (N < 1) return -1;
     if (nb < 1) return -4;
@@ -526,6 +572,9 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
     if (criterion == CRIT_FORCED && !forced) return -8;
     if (B && ldb < N) return -12;
     if (domain_stride < 0) return -21;
+    if (lu_variant < 0 || lu_variant > 2) return -22;
+    const int a2 = lu_variant == 2;
+    if (a2 && (domain_stride > 0 || invnorm_estimate || criterion == CRIT_MUMPS)) return -23;
 
     const int64_t n = (N + nb - 1) / nb;
     if (nsteps < 0 || nsteps > n) nsteps = n;
@@ -568,8 +617,18 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
 
         const int64_t d = domain_tiles(k, n, domain_stride, dtile);
         const int64_t R = (d - 1) * nb + tsize(N, nb, dtile[d - 1]);  /* rows of the stacked domain */
+        double *Tkk = Tq ? &Tq[((size_t)k * n + k) * nb * nb] : Tloc;
         int64_t zero_piv;
-        if (d == 1) {
+        if (a2) {
+            /* ---- Factor, variant A2 (Sec. 2.3): A_kk = Q_kk U_kk by GEQRT in
+             * place (V below the diagonal, U on and above it); no backup.  A
+             * zero on the diagonal of U marks a singular tile, as a zero GEPP
+             * pivot does in A1. */
+            oracle_geqrt(mk, Akk, lda, Tkk, nb);
+            zero_piv = 0;
+            for (int64_t c = 0; c < mk && !zero_piv; ++c)
+                if (Akk[IX(c, c, lda)] == 0.0) zero_piv = c + 1;
+        } else if (d == 1) {
         /* ---- Factor: backup copy W of A_kk, GEPP on the copy (Sec. 4, Backup Panel / LU On Panel) */
         for (int64_t j = 0; j < mk; ++j)
             for (int64_t i = 0; i < mk; ++i) W[IX(i, j, nb)] = Akk[IX(i, j, lda)];
@@ -609,7 +668,8 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
         int nonfinite = 0;
         if (!zero_piv) {
             /* ||A_kk^{-1}||_1 exactly, or its O(n_b^2) estimate (Sec. 3.4) */
-            double inv = invnorm_estimate ? oracle_inv_norm1_est(mk, W, nb) : oracle_inv_norm1(mk, W, nb, piv);
+            double inv = a2 ? oracle_inv_norm1_qr(mk, Akk, lda, Tkk, nb)
+                       : invnorm_estimate ? oracle_inv_norm1_est(mk, W, nb) : oracle_inv_norm1(mk, W, nb, piv);
             s = 1.0 / inv;
         }
         for (int64_t j = 0; j < mk; ++j) away[j] = 0.0;
@@ -689,35 +749,53 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
         if (margin_out) margin_out[k] = margin;
 
         if (lu) {
-            /* ---- LU step, variant A1 (Alg. 2) */
             if (zero_piv && diag && diag[DG_INFO] == 0.0) diag[DG_INFO] = (double)(k * nb + zero_piv);
-            for (int64_t j = 0; j < mk; ++j)
-                for (int64_t i = 0; i < mk; ++i) Akk[IX(i, j, lda)] = W[IX(i, j, nb)];
-            if (ipiv) for (int64_t c = 0; c < mk; ++c) ipiv[k * nb + c] = d == 1 ? piv[c] : dpiv[c];
-            if (d > 1) {
-                /* the domain's interchanges on the trailing columns of its rows
-                 * (and on B), and its multipliers below the diagonal tile; the
-                 * diagonal tile then needs no further pivoting (piv = identity) */
-                domain_swap(mk, dpiv, dtile, nb, A, lda, (k + 1) * nb, N);
-                if (B) domain_swap(mk, dpiv, dtile, nb, B, ldb, 0, nrhs);
-                for (int64_t t = 1; t < d; ++t)
-                    for (int64_t j = 0; j < mk; ++j)
-                        for (int64_t r = 0; r < tsize(N, nb, dtile[t]); ++r)
-                            A[IX(dtile[t] * nb + r, k * nb + j, lda)] = Wd[IX(t * nb + r, j, R)];
-            }
+            if (a2) {
+                /* ---- LU step, variant A2 (Sec. 2.3): Eliminate A_ik <- A_ik U_kk^{-1}
+                 * with U_kk the R factor in A_kk, Apply A_kj <- Q_kk^T A_kj (ORMQR) */
+                if (ipiv) for (int64_t c = 0; c < mk; ++c) ipiv[k * nb + c] = (int32_t)c;
 #pragma omp parallel for schedule(dynamic, 1)
-            for (int64_t t = 0; t < 2 * (n - k - 1); ++t) {
-                if (t < n - k - 1) { /* Eliminate A_ik (done by the domain factorization for its tiles) */
-                    int64_t i = k + 1 + t;
-                    int in_domain = 0;
-                    for (int64_t q = 1; q < d; ++q) in_domain |= dtile[q] == i;
-                    if (!in_domain) trsm_right_upper(mk, W, nb, tsize(N, nb, i), &A[IX(i * nb, k * nb, lda)], lda);
-                } else { /* Apply A_kj */
-                    int64_t j = k + 1 + (t - (n - k - 1));
-                    swptrsm(mk, W, nb, piv, tsize(N, nb, j), &A[IX(k * nb, j * nb, lda)], lda);
+                for (int64_t t = 0; t < 2 * (n - k - 1); ++t) {
+                    if (t < n - k - 1) {
+                        int64_t i = k + 1 + t;
+                        trsm_right_upper(mk, Akk, lda, tsize(N, nb, i), &A[IX(i * nb, k * nb, lda)], lda);
+                    } else {
+                        int64_t j = k + 1 + (t - (n - k - 1));
+                        oracle_unmqr(mk, Akk, lda, Tkk, nb, tsize(N, nb, j), &A[IX(k * nb, j * nb, lda)], lda);
+                    }
                 }
+                if (B) oracle_unmqr(mk, Akk, lda, Tkk, nb, nrhs, &B[IX(k * nb, 0, ldb)], ldb);
+            } else {
+                /* ---- LU step, variant A1 (Alg. 2) */
+                for (int64_t j = 0; j < mk; ++j)
+                    for (int64_t i = 0; i < mk; ++i) Akk[IX(i, j, lda)] = W[IX(i, j, nb)];
+                if (ipiv) for (int64_t c = 0; c < mk; ++c) ipiv[k * nb + c] = d == 1 ? piv[c] : dpiv[c];
+                if (d > 1) {
+                    /* the domain's interchanges on the trailing columns of its rows
+                     * (and on B), and its multipliers below the diagonal tile; the
+                     * diagonal tile then needs no further pivoting (piv = identity) */
+                    domain_swap(mk, dpiv, dtile, nb, A, lda, (k + 1) * nb, N);
+                    if (B) domain_swap(mk, dpiv, dtile, nb, B, ldb, 0, nrhs);
+                    for (int64_t t = 1; t < d; ++t)
+                        for (int64_t j = 0; j < mk; ++j)
+                            for (int64_t r = 0; r < tsize(N, nb, dtile[t]); ++r)
+                                A[IX(dtile[t] * nb + r, k * nb + j, lda)] = Wd[IX(t * nb + r, j, R)];
+                }
+#pragma omp parallel for schedule(dynamic, 1)
+                for (int64_t t = 0; t < 2 * (n - k - 1); ++t) {
+                    if (t < n - k - 1) { /* Eliminate A_ik (done by the domain factorization for its tiles) */
+                        int64_t i = k + 1 + t;
+                        int in_domain = 0;
+                        for (int64_t q = 1; q < d; ++q) in_domain |= dtile[q] == i;
+                        if (!in_domain) trsm_right_upper(mk, W, nb, tsize(N, nb, i), &A[IX(i * nb, k * nb, lda)], lda);
+                    } else { /* Apply A_kj */
+                        int64_t j = k + 1 + (t - (n - k - 1));
+                        swptrsm(mk, W, nb, piv, tsize(N, nb, j), &A[IX(k * nb, j * nb, lda)], lda);
+                    }
+                }
+                if (B) swptrsm(mk, W, nb, piv, nrhs, &B[IX(k * nb, 0, ldb)], ldb);
             }
-            if (B) swptrsm(mk, W, nb, piv, nrhs, &B[IX(k * nb, 0, ldb)], ldb);
+            /* ---- Update (both variants) */
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
             for (int64_t j = k + 1; j < n; ++j)
                 for (int64_t i = k + 1; i < n; ++i)
@@ -749,10 +827,10 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
             }
         } else {
             /* ---- QR step with TS kernels, flat tree: eliminator of every A_ik is A_kk (Alg. 3, 4a).
-             * A_kk was never modified (the LU attempt ran on the copy W: restore is a no-op). */
-            double *Tkk = Tq ? &Tq[((size_t)k * n + k) * nb * nb] : Tloc;
+             * A1: A_kk was never modified (the LU attempt ran on the copy W: restore
+             * is a no-op).  A2: the GEQRT of A_kk is the Factor's, kept (Sec. 2.3). */
             if (ipiv) for (int64_t c = 0; c < mk; ++c) ipiv[k * nb + c] = (int32_t)c;
-            oracle_geqrt(mk, Akk, lda, Tkk, nb);
+            if (!a2) oracle_geqrt(mk, Akk, lda, Tkk, nb);
 #pragma omp parallel for schedule(dynamic, 1)
             for (int64_t j = k + 1; j < n; ++j)
                 oracle_unmqr(mk, Akk, lda, Tkk, nb, tsize(N, nb, j), &A[IX(k * nb, j * nb, lda)], lda);
@@ -771,7 +849,7 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
                                  &B[IX(i * nb, 0, ldb)], ldb);
             }
         }
-        if (diag) diag[DG_TRUEFLOPS] += step_units(n - k - 1, !lu) * (double)nb * (double)nb * (double)nb;
+        if (diag) diag[DG_TRUEFLOPS] += step_units_v(n - k - 1, !lu, a2) * (double)nb * (double)nb * (double)nb;
     }
     if (diag) {
         diag[DG_GROWTH_TILE] = max_tile0 > 0 ? max_tile / max_tile0 : 0.0;
@@ -789,7 +867,7 @@ int oracle_factor_domain(int64_t N, double *A, int64_t lda, int64_t nb, int32_t 
                          double *margin_out, double *diag, int32_t domain_stride)
 {
     return oracle_factor_ex(N, A, lda, nb, criterion, alpha, seed, forced, mumps_reading, nsteps, B, ldb, nrhs,
-                            ipiv, Tq, dec, s_out, m_out, margin_out, diag, domain_stride, 0);
+                            ipiv, Tq, dec, s_out, m_out, margin_out, diag, domain_stride, 0, 1);
 }
 
 int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
@@ -807,9 +885,11 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
 /* then block back-substitution with the upper-triangular factor.  F, ipiv, */
 /* Tq, dec are oracle_factor outputs of a full factorization.              */
 /* ---------------------------------------------------------------------- */
-void oracle_forward_domain(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
-                           const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
-                           int32_t domain_stride)
+/* lu_variant 2: an LU step replays Q_kk^T (from V_kk and Tq(k,k)) on B_k
+ * before the block eliminations below it (Sec. 2.3). */
+void oracle_forward_v(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+                      const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
+                      int32_t domain_stride, int32_t lu_variant)
 {
     const int64_t n = (N + nb - 1) / nb;
     int64_t *dtile = (int64_t *)malloc((size_t)n * sizeof(int64_t));
@@ -820,7 +900,13 @@ void oracle_forward_domain(int64_t N, const double *F, int64_t ldf, int64_t nb, 
         const double *Fkk = &F[IX(k * nb, k * nb, ldf)];
         double *Bk = &B[IX(k * nb, 0, ldb)];
         const int64_t d = domain_tiles(k, n, domain_stride, dtile);
-        if (dec[k] && d > 1) {
+        if (dec[k] && lu_variant == 2) {
+            oracle_unmqr(mk, Fkk, ldf, &Tq[((size_t)k * n + k) * nb * nb], nb, nrhs, Bk, ldb);
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t i = k + 1; i < n; ++i)
+                gemm_minus(tsize(N, nb, i), nrhs, mk, &F[IX(i * nb, k * nb, ldf)], ldf, Bk, ldb,
+                           &B[IX(i * nb, 0, ldb)], ldb);
+        } else if (dec[k] && d > 1) {
             domain_swap(mk, &ipiv[k * nb], dtile, nb, B, ldb, 0, nrhs);
             swptrsm(mk, Fkk, ldf, ident, nrhs, Bk, ldb);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -841,6 +927,13 @@ void oracle_forward_domain(int64_t N, const double *F, int64_t ldf, int64_t nb, 
         }
     }
     free(dtile); free(ident);
+}
+
+void oracle_forward_domain(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+                           const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
+                           int32_t domain_stride)
+{
+    oracle_forward_v(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs, domain_stride, 1);
 }
 
 void oracle_forward(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
@@ -879,6 +972,14 @@ void oracle_solve_domain(int64_t N, const double *F, int64_t ldf, int64_t nb, co
                          int32_t domain_stride)
 {
     oracle_forward_domain(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs, domain_stride);
+    oracle_backward(N, F, ldf, nb, B, ldb, nrhs);
+}
+
+void oracle_solve_v(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+                    const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
+                    int32_t domain_stride, int32_t lu_variant)
+{
+    oracle_forward_v(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs, domain_stride, lu_variant);
     oracle_backward(N, F, ldf, nb, B, ldb, nrhs);
 }
 

@@ -60,7 +60,13 @@ def lib():
                                            dp, i64, i64, ip, dp, bp, dp, dp, dp, dp, i32]
         L.oracle_factor_ex.restype = C.c_int
         L.oracle_factor_ex.argtypes = [i64, dp, i64, i64, i32, f64, C.c_uint64, bp, i32, i64,
-                                       dp, i64, i64, ip, dp, bp, dp, dp, dp, dp, i32, i32]
+                                       dp, i64, i64, ip, dp, bp, dp, dp, dp, dp, i32, i32, i32]
+        L.oracle_inv_norm1_qr.restype = f64
+        L.oracle_inv_norm1_qr.argtypes = [i64, dp, i64, dp, i64]
+        L.oracle_solve_v.restype = None
+        L.oracle_solve_v.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64, i32, i32]
+        L.oracle_forward_v.restype = None
+        L.oracle_forward_v.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64, i32, i32]
         L.oracle_inv_norm1_est.restype = f64
         L.oracle_inv_norm1_est.argtypes = [i64, dp, i64]
         L.oracle_solve.restype = None
@@ -129,6 +135,7 @@ class OracleFactors:
     diag: np.ndarray         # see DG_*
     Bt: np.ndarray | None = None   # forward-transformed B in augmented mode
     domain: int = 0          # stride p of the diagonal domain (0: the diagonal tile alone)
+    variant: int = 1         # LU-step variant: 1 = A1 (Alg. 2), 2 = A2 (Sec. 2.3)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -140,12 +147,14 @@ class OracleFactors:
 
 
 def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading=0,
-           nsteps=-1, B=None, domain=0, estimate=False) -> OracleFactors:
+           nsteps=-1, B=None, domain=0, estimate=False, variant=1) -> OracleFactors:
     """Hybrid LU-QR factorization (Alg. 1) of a copy of A.  domain = p > 0
     pivots the LU attempt over the diagonal domain (the panel tiles k, k+p,
     k+2p, ...; Sec. 2.1), domain = 0 within the diagonal tile.  estimate:
     the criteria take ||A_kk^{-1}||_1 from the O(n_b^2) iterative estimate
-    (Sec. 3.4) instead of computing it exactly."""
+    (Sec. 3.4) instead of computing it exactly.  variant: the LU step, 1 =
+    A1 (GEPP on a backup of A_kk, Alg. 2), 2 = A2 (GEQRT of A_kk first, kept
+    by a QR step; Sec. 2.3)."""
     A = _fortran(A)
     N = A.shape[0]
     assert A.shape == (N, N)
@@ -167,10 +176,11 @@ def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading
     if B is not None:
         Bt = _fortran(B.reshape(N, -1) if B.ndim == 1 else B)
         nrhs = Bt.shape[1]
-    if estimate:
+    if estimate or variant != 1:
         rc = lib().oracle_factor_ex(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
                                     int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
-                                    _b(dec), _d(s), _d(m), _d(margin), _d(diag), int(domain), 1)
+                                    _b(dec), _d(s), _d(m), _d(margin), _d(diag), int(domain),
+                                    1 if estimate else 0, int(variant))
     elif domain:
         rc = lib().oracle_factor_domain(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
                                         int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
@@ -181,7 +191,7 @@ def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading
                                  _b(dec), _d(s), _d(m), _d(margin), _d(diag))
     if rc != 0:
         raise ValueError(f"oracle_factor rejected argument {-rc}")
-    return OracleFactors(N, nb, A, ipiv, Tq, dec, s, m, margin, diag, Bt, int(domain))
+    return OracleFactors(N, nb, A, ipiv, Tq, dec, s, m, margin, diag, Bt, int(domain), int(variant))
 
 
 def solve(fac: OracleFactors, B):
@@ -189,7 +199,10 @@ def solve(fac: OracleFactors, B):
     B = np.asarray(B, dtype=np.float64)
     vec = B.ndim == 1
     X = _fortran(B.reshape(fac.N, -1))
-    if fac.domain:
+    if fac.variant == 2:
+        lib().oracle_solve_v(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
+                             _d(X), fac.N, X.shape[1], fac.domain, 2)
+    elif fac.domain:
         lib().oracle_solve_domain(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
                                   _d(X), fac.N, X.shape[1], fac.domain)
     else:
@@ -200,8 +213,8 @@ def solve(fac: OracleFactors, B):
 
 def forward(fac: OracleFactors, B):
     X = _fortran(np.asarray(B, dtype=np.float64).reshape(fac.N, -1))
-    lib().oracle_forward_domain(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
-                                _d(X), fac.N, X.shape[1], fac.domain)
+    lib().oracle_forward_v(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
+                           _d(X), fac.N, X.shape[1], fac.domain, fac.variant)
     return X
 
 
@@ -232,6 +245,13 @@ def inv_norm1_est(LU):
     (Sec. 3.4; the permutation does not change the 1-norm)."""
     LU = _fortran(LU)
     return lib().oracle_inv_norm1_est(LU.shape[0], _d(LU), LU.shape[0])
+
+
+def inv_norm1_qr(VR, T):
+    """||A^{-1}||_1 from the GEQRT factors of A (V\\R and T; variant A2, Sec. 2.3)."""
+    VR = _fortran(VR)
+    T = _fortran(T)
+    return lib().oracle_inv_norm1_qr(VR.shape[0], _d(VR), VR.shape[0], _d(T), T.shape[0])
 
 
 def tile_norm1(A):
