@@ -73,6 +73,9 @@ def parse():
                          "profiled runs skip the factorizations that build U and V)")
     ap.add_argument("--estimate", action="store_true",
                     help="take ||A_kk^-1||_1 from the O(n_b^2) iterative estimate (Sec. 3.4) instead of exactly")
+    ap.add_argument("--lu-variant", type=int, default=1, choices=(1, 2),
+                    help="LU step: 1 = A1 (GEPP on a backup of A_kk, Alg. 2); 2 = A2 (GEQRT of A_kk first, "
+                         "kept by a QR step; Sec. 2.3)")
     ap.add_argument("--dump-steps", default="", metavar="PATH",
                     help="write the per-step phase durations (mean over the timed steps), decisions and margins "
                          "of the timed path to PATH as JSON")
@@ -122,6 +125,17 @@ def qr_step_flops(n, nb, dec):
     2 (2/3 + 2 r + 2 r^2) n_b^3 flops (GEQRT, TSQRT, UNMQR, TSMQR)."""
     r = n - 1 - np.arange(n)
     return float(np.sum((dec == 0) * 2.0 * (2.0 / 3.0 + 2.0 * r + 2.0 * r * r)) * nb ** 3)
+
+
+def lu_step_flops(n, nb, dec, variant=1):
+    """Tab. 1: an LU step costs (2/3 + 2 r + 2 r^2) n_b^3 flops (GETRF, TRSM,
+    TRSM, GEMM); variant A2 doubles its Factor and Apply (Sec. 2.3):
+    (4/3 + 3 r + 2 r^2) n_b^3."""
+    r = n - 1 - np.arange(n)
+    u = 2.0 / 3.0 + 2.0 * r + 2.0 * r * r
+    if variant == 2:
+        u = u + 2.0 / 3.0 + r
+    return float(np.sum((dec == 1) * u) * nb ** 3)
 
 
 def lu_update_flops(n, nb, dec):
@@ -196,7 +210,8 @@ def cpu_baseline(args, solver, torch):
     A = inputs.usv(Ns, args.kappa, seed=(args.seed,))
     b = inputs.rhs(Ns, 1, seed=(args.seed,))
     t0 = time.perf_counter()
-    fo = O.factor(A, args.nb, args.criterion, args.alpha, seed=args.seed)
+    fo = O.factor(A, args.nb, args.criterion, args.alpha, seed=args.seed, estimate=args.estimate,
+                  variant=args.lu_variant)
     xo = fo.solve(b)
     t = time.perf_counter() - t0
     eta_o = O.backward_error(A, xo, b)
@@ -204,7 +219,7 @@ def cpu_baseline(args, solver, torch):
     Ad = torch.from_numpy(A).cuda()
     bd = torch.from_numpy(b).cuda()
     f = solver.factor(Ad, args.nb, criterion=args.criterion, alpha=args.alpha, seed=args.seed,
-                      precision=args.precision)
+                      precision=args.precision, estimate=args.estimate, variant=args.lu_variant)
     x = f.solve_refined(Ad, bd, max_iter=args.max_iter) if args.precision != "fp64" else f.solve(bd)
     dec, _, _, mg = f.decisions()
     band = DECISION_BAND[args.precision]
@@ -216,7 +231,7 @@ def cpu_baseline(args, solver, torch):
         "cores": O.num_threads(),
         "kind": "oracle",
         "sample": f"FP64 oracle factor+solve, usv kappa={args.kappa:g} N={Ns} nb={args.nb} "
-                  f"{args.criterion} alpha={args.alpha:g}, 1 RHS ({t:.1f} s)",
+                  f"{args.criterion} alpha={args.alpha:g}{' A2' if args.lu_variant == 2 else ''}, 1 RHS ({t:.1f} s)",
         "seconds": round(t, 3),
         "eta_oracle": eta_o,
         "eta_gpu": eta_g,
@@ -428,7 +443,8 @@ def main():
     B = torch.from_numpy(np.asfortranarray(inputs.rhs(N, args.nrhs, seed=(args.seed,)).reshape(N, -1))).cuda()
     B = B.t().contiguous().t()
     torch.cuda.synchronize()
-    kw = dict(criterion=args.criterion, alpha=args.alpha, seed=args.seed, nrhs_max=args.nrhs, estimate=args.estimate)
+    kw = dict(criterion=args.criterion, alpha=args.alpha, seed=args.seed, nrhs_max=args.nrhs, estimate=args.estimate,
+              variant=args.lu_variant)
 
     nb64 = min(nb, 256)  # the FP64 path stops at n_b = 256
 
@@ -525,7 +541,8 @@ def main():
                    "N": N, "nb": nb, "nrhs": args.nrhs, "kappa": args.kappa, "criterion": args.criterion,
                    "refine": args.refine,
                    "alpha": args.alpha, "precision": prec, "parallelism": "single GPU",
-                   "inverse_norm": "estimate" if args.estimate else "exact"},
+                   "inverse_norm": "estimate" if args.estimate else "exact",
+                   "lu_variant": "A2" if args.lu_variant == 2 else "A1"},
         "solves_per_s": round(1e3 / ms, 4),
         "eta": eta,
         "eta_target": N * 1e-16,
@@ -534,9 +551,8 @@ def main():
         "watchdog": st.watchdog,
         "lu_steps": int(dec.sum()),
         "decisions": "".join("L" if d else "Q" for d in dec),
-        "true_tflops": round((qr_step_flops(n, nb, dec) + float(np.sum(
-            (dec == 1) * (2.0 / 3.0 + 2.0 * (n - 1 - np.arange(n)) + 2.0 * (n - 1 - np.arange(n)) ** 2)) * nb ** 3))
-            / (ms * 1e-3) / 1e12, 3),
+        "true_tflops": round((qr_step_flops(n, nb, dec) + lu_step_flops(n, nb, dec, args.lu_variant))
+                             / (ms * 1e-3) / 1e12, 3),
         "factor_ms_events": round(fac_ms, 3),
         "phase_ms": phase_ms,
         "fp64": fp64,

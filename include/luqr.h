@@ -100,6 +100,18 @@ typedef struct {
                             estimate is a lower bound, so s_k = 1/est can only be larger
                             than the exact one: an LU step of the exact criterion stays
                             LU.  Not by the batched entry points. */
+    int32_t lu_variant;  /* LU step variant.  0 or 1 (default): A1 (Alg. 2): the panel
+                            factors an FP64 backup copy of A_kk by GEPP and a QR step
+                            starts afresh from the untouched tile.  2: A2 (Sec. 2.3):
+                            every step first QR-factors A_kk in place (GEQRT, storage
+                            precision, V and R kept in the tile, no backup); the
+                            criterion takes ||A_kk^-1||_1 = ||R^-1 Q^T||_1 (FP64, from
+                            those factors); an LU step eliminates with R (A_ik R^-1),
+                            applies Q^T to the tiles A_kj and updates as in A1; a QR
+                            step continues from the same GEQRT.  Pivots of an A2 LU step
+                            are the identity.  With Max, Sum, Random and Forced only,
+                            without a domain or the estimate (else LUQR_ERR_UNSUPPORTED);
+                            not by the batched entry points. */
 } luqr_opts;
 
 /* Device-side numerical status, read back by luqr_get_status. */

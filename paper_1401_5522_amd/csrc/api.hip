@@ -64,6 +64,9 @@ static int check_opts(int64_t N, const luqr_opts *o, int pos_opts) {
     if (o->criterion == LUQR_CRIT_FORCED && !o->forced) return -pos_opts;
     if (o->domain_stride < 0) return -pos_opts;
     if (o->invnorm_estimate < 0 || o->invnorm_estimate > 1) return -pos_opts;
+    if (o->lu_variant < 0 || o->lu_variant > 2) return -pos_opts;
+    if (o->lu_variant == 2 && (o->criterion == LUQR_CRIT_MUMPS || o->domain_stride > 0 || o->invnorm_estimate))
+        return LUQR_ERR_UNSUPPORTED;  // A2 has no GEPP pivots, domain or triangular L^-1 for these
     if (!pick_ops(o->nb, o->precision)) return LUQR_ERR_UNSUPPORTED;
     if (o->domain_stride > 0) {  // the domain's GEPP holds at most 512 stacked rows in one workgroup
         const int64_t n = (N + o->nb - 1) / o->nb;
@@ -95,7 +98,7 @@ extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_
     luqr_factors_s *f = new (std::nothrow) luqr_factors_s;
     if (!f) return LUQR_ERR_HIP - (int)hipErrorOutOfMemory;
     f->L = L;
-    f->c = make_ctx(L, dWork);
+    f->c = make_ctx(L, dWork, o->lu_variant == 2);
     f->ops = pick_ops(o->nb, o->precision);
     f->base = dWork;
     f->stream = (hipStream_t)stream;
@@ -531,7 +534,7 @@ extern "C" int luqr_solve_noalloc(int64_t N, const double *dA, int64_t lda, cons
     rc = scratch_for_current_device(&base);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    const Ctx c = make_ctx(L, base);
+    const Ctx c = make_ctx(L, base, o->lu_variant == 2);
     const Ops *ops = pick_ops(o->nb, o->precision);
     luqr_opts oo = *o;
     oo.no_lookahead = 1;                           // one stream: no side stream to create

@@ -316,7 +316,7 @@ struct Ctx {
                      // per-block factors the QR step uses, the rest is filled after the step
     double *gram;    // per panel tile of the current QR step: V^T V (nb x nb, upper IB-blocks)
     double *W;       // per step: FP64 copy of A_kk, factored in place (L\U)
-    double *Linv;    // per step: L_kk^{-1} (unit lower)
+    double *Linv;    // per step: L_kk^{-1} (unit lower), or Q_kk^T (variant A2)
     double *Dinv;    // per step: inverse of the upper-triangular diagonal factor (U or R)
     int *ipiv;       // per step: GETRF interchanges (local rows)
     int *perm;       // per step: row permutation, (P A)(r,:) = A(perm[r],:)
@@ -335,6 +335,7 @@ struct Ctx {
     int64_t N, n;
     int nb;
     int dstride, DR;
+    int a2;          // LU steps of variant A2 (GEQRT of A_kk first; Linv holds Q_kk^T, perm the identity)
     // tiles in the diagonal domain of step k, and whether tile row i > k is one of them
     LQ_HD int dcount(int64_t k) const { return 1 + (dstride > 0 ? (int)((n - 1 - k) / dstride) : 0); }
     LQ_HD bool indom(int64_t k, int64_t i) const { return dstride > 0 && i > k && (i - k) % dstride == 0; }
@@ -344,7 +345,7 @@ struct Ctx {
     LQ_HD int msize(int64_t k) const { return (int)((k < n - 1) ? nb : N - (n - 1) * (int64_t)nb); }
 };
 
-inline Ctx make_ctx(const Layout &L, void *base) {
+inline Ctx make_ctx(const Layout &L, void *base, int a2 = 0) {
     char *b = (char *)base;
     Ctx c;
     c.At = b + L.off_At; c.Tf = b + L.off_Tf; c.gram = (double *)(b + L.off_gram); c.W = (double *)(b + L.off_W);
@@ -358,6 +359,7 @@ inline Ctx make_ctx(const Layout &L, void *base) {
     c.WD = (double *)(b + L.off_WD); c.dperm = (int *)(b + L.off_dperm);
     c.N = L.N; c.n = L.n; c.nb = (int)L.nb;
     c.dstride = L.dstride; c.DR = (int)L.DR;
+    c.a2 = a2;
     return c;
 }
 

@@ -56,13 +56,20 @@ struct Eng {
             const int rest = n - k - 1;
             if (ev) (void)hipEventRecord(ev[E * k + 0], st);
             if (rest > 0) k_panel_norms<NB, S><<<rest, WG, 0, st>>>(c, k);
-            if constexpr (NB <= 256) {
-                if (c.dcount(k) > 1) k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);  // up to 512 stacked rows
-                else k_panel_getrf<NB, S, 1><<<1, WG, 0, st>>>(c, k);
+            if (c.a2) {
+                // variant A2: GEQRT of A_kk in place, then R^{-1} and Q^T in FP64
+                k_qr_step<NB, P><<<qr_pw<NB>(), WG, 0, st>>>(c, k, QR_GEQRT);
+                k_qr_rinv<NB, S><<<NB / 4, WG, 0, st>>>(c, k, 1);
+                k_a2_qt<NB, S><<<NB / 16, WG, 0, st>>>(c, k);
             } else {
-                k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);
+                if constexpr (NB <= 256) {
+                    if (c.dcount(k) > 1) k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);  // up to 512 stacked rows
+                    else k_panel_getrf<NB, S, 1><<<1, WG, 0, st>>>(c, k);
+                } else {
+                    k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);
+                }
+                k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
             }
-            k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
             if (o.invnorm_estimate) k_panel_invest<NB><<<1, WG, 0, st>>>(c, k);
             else k_panel_invnorm<NB><<<(NB / B) * (NB / B), WG, 0, st>>>(c, k);
             DecideArgs a;
@@ -82,7 +89,7 @@ struct Eng {
                 k_lu_update<NB, P><<<(unsigned)rest * cols * PER * PER, WG, 0, st>>>(c, k, k + 1);
             }
             if (ev) (void)hipEventRecord(ev[E * k + 3], st);
-            k_qr_step<NB, P><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k);
+            k_qr_step<NB, P><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k, c.a2 ? QR_REST : QR_FULL);
             if (ev) (void)hipEventRecord(ev[E * k + 4], st);
             hipStream_t sb = st;
             if (side) {
@@ -91,7 +98,8 @@ struct Eng {
                 sb = side->st;
                 if (rest > 1) k_lu_update<NB, P><<<(unsigned)rest * (rest - 1) * PER * PER, WG, 0, sb>>>(c, k, k + 2);
             }
-            k_qr_rinv<NB, S><<<NB / 4, WG, 0, sb>>>(c, k);
+            // QR steps: R_kk after every TSQRT (A2's panel inverted the GEQRT's R for the criterion)
+            k_qr_rinv<NB, S><<<NB / 4, WG, 0, sb>>>(c, k, 0);
             if constexpr (NB > IB) {
                 k_qr_gram<NB, P><<<dim3(qr_npairs<NB>(), n - k), WG, 0, sb>>>(c, k);
                 k_qr_tfull<NB, P><<<n - k, WG, 0, sb>>>(c, k);
@@ -113,7 +121,7 @@ struct Eng {
             // the forward pass as one wavefront launch; the tile counters reuse
             // the QR steps' flags (n * nb/IB ints, free once the factorization is done)
             const int wch = (s.nrhs + FW_RQ - 1) / FW_RQ;
-            if (c.dstride == 0 && wch <= 4) {
+            if (c.dstride == 0 && !c.a2 && wch <= 4) {  // its LU rows take L^{-1} as unit lower
                 k_fill_int<<<nblk((int64_t)n * wch), WG, 0, st>>>(c.flags, (int64_t)n * wch, 0);
                 k_fwd_wave<NB, S><<<dim3(n, wch), FW_WG, 0, st>>>(c, s, c.flags);
                 wave = true;

@@ -4,6 +4,9 @@
 //   Eliminate A_ik <- A_ik U^{-1}      (i > k),
 //   Apply     A_kj <- L^{-1} P A_kj    (j > k),
 //   Update    A_ij <- A_ij - A_ik A_kj (i, j > k).
+// Variant A2 (Sec. 2.3) runs the same kernels with U^{-1} = R_kk^{-1},
+// L^{-1} = Q_kk^T and P = I from its GEQRT panel; its Factor is that GEQRT,
+// already in the tile.
 // Eliminate and Apply multiply by the explicit triangular inverses computed
 // for the criterion, so all three are MFMA contractions; each in-place
 // product is computed by a workgroup that owns whole rows (Eliminate) or
@@ -41,6 +44,7 @@ __global__ __launch_bounds__(WG) void k_lu_apply(Ctx c, int k) {
     int b = blockIdx.x;
     S *At = (S *)c.At;
     if (b == 0) {  // commit the factored copy (L\U) to the diagonal tile
+        if (c.a2) return;  // variant A2: the tile already holds V\R of its GEQRT
         const double *W = c.W + (size_t)k * NB * NB;
         S *Akk = At + c.toff(k, k);
         for (int e = threadIdx.x; e < NB * NB; e += WG) Akk[e] = (S)W[e];

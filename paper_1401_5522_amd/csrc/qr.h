@@ -537,10 +537,17 @@ template <int NB> constexpr int qr_pw() { return NB / IB; }  // producer workgro
 
 LQ_DEV int *qr_flag(const Ctx &c, int i, int b) { return &c.flags[(size_t)i * (c.nb / IB) + b]; }
 
+// What one k_qr_step launch runs.  Variant A2 (Sec. 2.3) splits a step at its
+// GEQRT: the panel factors A_kk before the decision (QR_GEQRT: producers only,
+// unit i = k; it publishes the flags of tile k), and a QR step then continues
+// from it (QR_REST: producers from i = k+1, consumers as in QR_FULL, their
+// UNMQR blocks waiting on the flags already set).
+enum QrMode { QR_FULL = 0, QR_GEQRT = 1, QR_REST = 2 };
+
 // Producer workgroup b of one QR step: block b of GEQRT(A_kk), then block b
-// of each TSQRT(A_kk, A_ik) in order of i.
+// of each TSQRT(A_kk, A_ik) in order of i (units i0..i1-1 by the mode).
 template <int NB, int P, bool PRE>
-LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
+LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem, int mode) {
     typedef typename Tr<P>::S S;
     constexpr int PP = (P == PB16) ? P32 : P;  // panel-internal updates stay in the storage precision
     S *Ys = (S *)smem;
@@ -554,7 +561,8 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem) {
     const int epoch = k + 1;
     const int c0 = b * IB;
     S *Akk = At + c.toff(k, k);
-    for (int i = k; i < c.n; ++i) {
+    const int i0 = mode == QR_REST ? k + 1 : k, i1 = mode == QR_GEQRT ? k + 1 : (int)c.n;
+    for (int i = i0; i < i1; ++i) {
         if (b > 0) {  // the trailing update of unit (i, b-1) must be in place
             if (tid == 0) bail = !flag_wait(qr_flag(c, i, b - 1), epoch, &c.st->watchdog);
             __syncthreads();
@@ -602,8 +610,8 @@ template <int NB, int P> constexpr int qr_step_lds() {
 template <int NB, int P> constexpr int qr_occ() { return qr_step_lds<NB, P>() <= 80 * 1024 ? 2 : 1; }
 
 template <int NB, int P>
-__global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k) {
-    if (c.dec[k] != 0) return;
+__global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k, int mode) {
+    if (mode != QR_GEQRT && c.dec[k] != 0) return;  // the A2 panel's GEQRT runs before the decision
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
     constexpr int VB = qr_vblk<NB>();
@@ -611,7 +619,7 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k)
     constexpr bool PRE = false;  // bulk operand loads would exceed the registers at nb >= 256
     __shared__ __attribute__((aligned(16))) char smem[qr_step_lds<NB, P>()];
     if ((int)blockIdx.x < qr_pw<NB>()) {
-        qr_producer<NB, P, PRE>(c, k, (int)blockIdx.x, smem);
+        qr_producer<NB, P, PRE>(c, k, (int)blockIdx.x, smem, mode);
         return;
     }
     // Consumer: one 64-column strip of trailing tile column j.  The blocks it

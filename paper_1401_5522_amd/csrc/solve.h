@@ -113,7 +113,8 @@ static __global__ __launch_bounds__(WG) void k_fwd_dswap(Ctx c, SolveArgs s, int
     }
 }
 
-// LU step, part 1: z_k = L^{-1} P y_k (L^{-1} from the panel, FP64).
+// LU step, part 1: z_k = L^{-1} P y_k (L^{-1} from the panel, FP64; for
+// variant A2, z_k = Q_kk^T y_k).
 // grid (nb / RB row blocks, rhs chunks).
 template <int NB>
 static __global__ __launch_bounds__(WG) void k_fwd_lu_a(Ctx c, SolveArgs s, int k) {
@@ -131,7 +132,9 @@ static __global__ __launch_bounds__(WG) void k_fwd_lu_a(Ctx c, SolveArgs s, int 
     }
     __syncthreads();
     double out[RQ];
-    if (rows_mv<NB, 2>(c.Linv + (size_t)k * NB * NB, ys, nq, r0, out, red))
+    const double *Li = c.Linv + (size_t)k * NB * NB;
+    // variant A2: Linv holds the dense Q_kk^T and perm is the identity
+    if (c.a2 ? rows_mv<NB, 0>(Li, ys, nq, r0, out, red) : rows_mv<NB, 2>(Li, ys, nq, r0, out, red))
         for (int q = 0; q < nq; ++q) s.Z[k * NB + r0 + lane_id() + (q0 + q) * Np] = out[q];
 }
 

@@ -31,6 +31,7 @@ def test_struct_layouts_match_header():
     from paper_1401_5522_amd import _lib
     assert C.sizeof(_lib.luqr_opts) == 64
     assert _lib.luqr_opts.invnorm_estimate.offset == 56
+    assert _lib.luqr_opts.lu_variant.offset == 60
     assert _lib.luqr_opts.forced.offset == 32
     assert C.sizeof(_lib.luqr_status) == 40
     assert _lib.luqr_status.ir_eta.offset == 24
@@ -76,3 +77,26 @@ def test_domain_stride_validation_without_gpu():
     assert L.luqr_workspace_bytes(1024, C.byref(o)) == _lib.LUQR_ERR_UNSUPPORTED
     o, _ = _lib.make_opts(128, domain=-1)
     assert L.luqr_workspace_bytes(1024, C.byref(o)) == -2
+
+
+def test_lu_variant_validation_without_gpu():
+    from paper_1401_5522_amd import _lib
+    L = _lib.lib()
+    for v in (0, 1, 2):
+        o, _ = _lib.make_opts(64, variant=v)
+        assert L.luqr_workspace_bytes(256, C.byref(o)) > 0
+    o, _ = _lib.make_opts(64, variant=3)
+    assert L.luqr_workspace_bytes(256, C.byref(o)) == -2
+    o, _ = _lib.make_opts(64, variant=-1)
+    assert L.luqr_workspace_bytes(256, C.byref(o)) == -2
+    # A2 has no GEPP pivots (MUMPS), no stacked domain and no unit-lower L^-1 (estimate)
+    for kw in (dict(criterion="mumps"), dict(domain=1), dict(estimate=True)):
+        o, _ = _lib.make_opts(64, variant=2, **kw)
+        assert L.luqr_workspace_bytes(256, C.byref(o)) == _lib.LUQR_ERR_UNSUPPORTED, kw
+    o, _ = _lib.make_opts(64, precision="fp32", variant=2)  # batched: FP32 and A1 only, checked before any GPU call
+    plan = C.c_void_p()
+    Ns = np.array([64], np.int64)
+    ld = np.array([64], np.int64)
+    rc = L.luqr_batched_plan(1, Ns.ctypes.data, None, ld.ctypes.data, ld.ctypes.data, ld.ctypes.data, C.byref(o),
+                             4, C.c_void_p(256), 1 << 30, C.byref(plan))
+    assert rc == _lib.LUQR_ERR_UNSUPPORTED
