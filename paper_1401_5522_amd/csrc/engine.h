@@ -57,10 +57,13 @@ struct Eng {
             if (ev) (void)hipEventRecord(ev[E * k + 0], st);
             if (rest > 0) k_panel_norms<NB, S><<<rest, WG, 0, st>>>(c, k);
             if (c.a2) {
-                // variant A2: GEQRT of A_kk in place, then R^{-1} and Q^T in FP64
-                k_qr_step<NB, P><<<qr_pw<NB>(), WG, 0, st>>>(c, k, QR_GEQRT);
-                k_qr_rinv<NB, S><<<NB / 4, WG, 0, st>>>(c, k, 1);
-                k_a2_qt<NB, S><<<NB / 16, WG, 0, st>>>(c, k);
+                // variant A2: GEQRT of A_kk (FP64, on a working copy), Q^T, the
+                // rounded factors into the tile, R^{-1}
+                k_a2_copy<NB, S><<<NB * NB / (4 * WG), WG, 0, st>>>(c, k);
+                k_a2_geqrt<NB><<<qr_pw<NB>(), WG, 0, st>>>(c, k);
+                k_a2_qt<NB><<<NB / 16, WG, 0, st>>>(c, k);
+                k_a2_commit<NB, S><<<NB * NB / (4 * WG), WG, 0, st>>>(c, k);
+                k_a2_rinv<NB><<<NB / 4, WG, 0, st>>>(c, k);
             } else {
                 if constexpr (NB <= 256) {
                     if (c.dcount(k) > 1) k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);  // up to 512 stacked rows
@@ -99,7 +102,7 @@ struct Eng {
                 if (rest > 1) k_lu_update<NB, P><<<(unsigned)rest * (rest - 1) * PER * PER, WG, 0, sb>>>(c, k, k + 2);
             }
             // QR steps: R_kk after every TSQRT (A2's panel inverted the GEQRT's R for the criterion)
-            k_qr_rinv<NB, S><<<NB / 4, WG, 0, sb>>>(c, k, 0);
+            k_qr_rinv<NB, S><<<NB / 4, WG, 0, sb>>>(c, k);
             if constexpr (NB > IB) {
                 k_qr_gram<NB, P><<<dim3(qr_npairs<NB>(), n - k), WG, 0, sb>>>(c, k);
                 k_qr_tfull<NB, P><<<n - k, WG, 0, sb>>>(c, k);
@@ -121,7 +124,7 @@ struct Eng {
             // the forward pass as one wavefront launch; the tile counters reuse
             // the QR steps' flags (n * nb/IB ints, free once the factorization is done)
             const int wch = (s.nrhs + FW_RQ - 1) / FW_RQ;
-            if (c.dstride == 0 && !c.a2 && wch <= 4) {  // its LU rows take L^{-1} as unit lower
+            if (c.dstride == 0 && wch <= 4) {
                 k_fill_int<<<nblk((int64_t)n * wch), WG, 0, st>>>(c.flags, (int64_t)n * wch, 0);
                 k_fwd_wave<NB, S><<<dim3(n, wch), FW_WG, 0, st>>>(c, s, c.flags);
                 wave = true;

@@ -717,41 +717,76 @@ __global__ __launch_bounds__(WG) void k_panel_decide(Ctx c, int k, DecideArgs a)
 }
 
 // QR steps: Dinv_k <- R_kk^{-1} from the upper triangle of the factored tile.
-// always = 1: the panel of variant A2, before the decision (both branches
-// use R^{-1}).
 template <int NB, class S>
-__global__ __launch_bounds__(WG) void k_qr_rinv(Ctx c, int k, int always) {
-    if (!always && c.dec[k] != 0) return;
+__global__ __launch_bounds__(WG) void k_qr_rinv(Ctx c, int k) {
+    if (c.dec[k] != 0) return;
     trtri_col<NB, S>((const S *)c.At + c.toff(k, k), c.Dinv + (size_t)k * NB * NB, true);
 }
 
-// Panel of variant A2 (Sec. 2.3), after the GEQRT of A_kk: Linv_k <- Q_kk^T
-// in FP64, so that the criterion's ||A_kk^{-1}||_1 = ||R^{-1} Q^T||_1, the
-// Apply (A_kj <- Q^T A_kj) and the solve's z_k = Q^T y_k are the A1 products
-// with L^{-1}; perm_k <- identity; zpiv_k <- first zero on R's diagonal
-// (1-based) over the tile's real columns; ipiv_k <- identity.  Q = Q_0 Q_1 .. Q_{B-1} with Q_b =
-// I - V_b T_b V_b^T the IB-column blocks of the GEQRT (V unit lower in the
-// tile, T_b the diagonal blocks of the T factor of tile (k,k)), so Q^T is
-// the identity with Q_0^T, Q_1^T, .. applied in turn.  Grid NB/16: each
-// workgroup forms 16 columns, held in LDS with the current block of V.
+// ---------------------------------------------------------------------------
+// Panel of variant A2 (Sec. 2.3).  Its Factor is a QR factorization of A_kk;
+// here it runs in FP64 on a working copy W_k (k_a2_copy, k_a2_geqrt), so the
+// criterion's ||A_kk^{-1}||_1 is taken from FP64 factors in every storage
+// precision, as A1's is from its FP64 GEPP.  The copy is no backup: nothing is
+// restored from it, and the storage tile receives the rounded V\R and T
+// (k_a2_commit) for the branch that follows, LU or QR alike.
+// ---------------------------------------------------------------------------
 template <int NB, class S>
+__global__ __launch_bounds__(WG) void k_a2_copy(Ctx c, int k) {
+    const S *A = (const S *)c.At + c.toff(k, k);
+    double *W = c.W + (size_t)k * NB * NB;
+    for (int e = blockIdx.x * WG + threadIdx.x; e < NB * NB; e += gridDim.x * WG) W[e] = (double)A[e];
+}
+
+// Last of the A2 panel (both branches use it): Dinv_k <- R^{-1} from the FP64
+// R of the GEQRT on W_k (overwriting the T factor kept there).
+template <int NB>
+__global__ __launch_bounds__(WG) void k_a2_rinv(Ctx c, int k) {
+    trtri_col<NB, double>(c.W + (size_t)k * NB * NB, c.Dinv + (size_t)k * NB * NB, true);
+}
+
+// After k_a2_qt (which reads T from the Dinv_k slot): tile (k,k) <- V\R and
+// the diagonal IB-blocks of its T factor <- T, both rounded to storage.
+template <int NB, class S>
+__global__ __launch_bounds__(WG) void k_a2_commit(Ctx c, int k) {
+    S *A = (S *)c.At + c.toff(k, k);
+    S *T = (S *)c.Tf + c.tqoff(k, k);
+    const double *W = c.W + (size_t)k * NB * NB;
+    const double *T64 = c.Dinv + (size_t)k * NB * NB;
+    for (int e = blockIdx.x * WG + threadIdx.x; e < NB * NB; e += gridDim.x * WG) {
+        A[e] = (S)W[e];
+        const int r = e % NB, col = e / NB;
+        if (r / IB == col / IB) T[e] = (S)T64[e];
+    }
+}
+
+// Linv_k <- Q_kk^T in FP64, so that the criterion's ||A_kk^{-1}||_1 =
+// ||R^{-1} Q^T||_1, the Apply (A_kj <- Q^T A_kj) and the solve's z_k = Q^T y_k
+// are the A1 products with L^{-1}; perm_k and ipiv_k <- identity; zpiv_k <-
+// first zero on R's diagonal (1-based) over the tile's real columns.  Q = Q_0
+// Q_1 .. Q_{B-1} with Q_b = I - V_b T_b V_b^T the IB-column blocks of the
+// GEQRT (V unit lower in W_k, T_b the diagonal blocks of its T factor, in the
+// Dinv_k slot), so Q^T is the identity with Q_0^T, Q_1^T, .. applied in turn.
+// Grid NB/16: each workgroup forms 16 columns, held in LDS with the current
+// block of V.
+template <int NB>
 __global__ __launch_bounds__(WG) void k_a2_qt(Ctx c, int k) {
     static_assert(IB == 16, "one thread per (reflector, column) of a block");
     __shared__ double C[NB * 16];   // C[r*16 + col]: column cb*16 + col of the running product
     __shared__ double Vs[IB * NB];  // Vs[q*NB + r] = V(r, c0 + q), zeros and ones explicit
     __shared__ double Ts[IB * IB], Wb[IB * 16], Wt[IB * 16];
     const int tid = threadIdx.x, cb = blockIdx.x;
-    const S *A = (const S *)c.At + c.toff(k, k);
-    const S *T = (const S *)c.Tf + c.tqoff(k, k);
+    const double *A = c.W + (size_t)k * NB * NB;
+    const double *T = c.Dinv + (size_t)k * NB * NB;
     for (int e = tid; e < NB * 16; e += WG) C[e] = (e / 16 == cb * 16 + e % 16) ? 1.0 : 0.0;
     const int p = tid / 16, col = tid % 16;
     for (int b = 0; b < NB / IB; ++b) {
         const int c0 = b * IB;
         for (int e = tid; e < IB * NB; e += WG) {
             const int q = e / NB, r = e % NB;
-            Vs[e] = r < c0 + q ? 0.0 : (r == c0 + q ? 1.0 : (double)A[r + (size_t)(c0 + q) * NB]);
+            Vs[e] = r < c0 + q ? 0.0 : (r == c0 + q ? 1.0 : A[r + (size_t)(c0 + q) * NB]);
         }
-        Ts[tid] = (double)T[(c0 + tid % IB) + (size_t)(c0 + tid / IB) * NB];  // Ts[q*IB + p] = T(p, q)
+        Ts[tid] = T[(c0 + tid % IB) + (size_t)(c0 + tid / IB) * NB];  // Ts[q*IB + p] = T(p, q)
         __syncthreads();
         double w = 0.0;  // W = V_b^T C
         for (int r = c0 + p; r < NB; ++r) w += Vs[p * NB + r] * C[r * 16 + col];
@@ -779,7 +814,7 @@ __global__ __launch_bounds__(WG) void k_a2_qt(Ctx c, int k) {
             int zp = 0;
             const int mk = c.msize(k);
             for (int j = 0; j < mk && !zp; ++j)
-                if ((double)A[j + (size_t)j * NB] == 0.0) zp = j + 1;
+                if (A[j + (size_t)j * NB] == 0.0) zp = j + 1;
             c.zpiv[k] = zp;
         }
     }

@@ -537,17 +537,20 @@ template <int NB> constexpr int qr_pw() { return NB / IB; }  // producer workgro
 
 LQ_DEV int *qr_flag(const Ctx &c, int i, int b) { return &c.flags[(size_t)i * (c.nb / IB) + b]; }
 
-// What one k_qr_step launch runs.  Variant A2 (Sec. 2.3) splits a step at its
-// GEQRT: the panel factors A_kk before the decision (QR_GEQRT: producers only,
-// unit i = k; it publishes the flags of tile k), and a QR step then continues
-// from it (QR_REST: producers from i = k+1, consumers as in QR_FULL, their
-// UNMQR blocks waiting on the flags already set).
+// What the producers of one launch run.  Variant A2 (Sec. 2.3) splits a step
+// at its GEQRT: the panel factors A_kk before the decision (QR_GEQRT: unit
+// i = k only, k_a2_geqrt; it publishes the flags of tile k), and a QR step
+// then continues from it (QR_REST: producers from i = k+1, consumers as in
+// QR_FULL, their UNMQR blocks waiting on the flags already set).
 enum QrMode { QR_FULL = 0, QR_GEQRT = 1, QR_REST = 2 };
 
 // Producer workgroup b of one QR step: block b of GEQRT(A_kk), then block b
 // of each TSQRT(A_kk, A_ik) in order of i (units i0..i1-1 by the mode).
+// akk, tkk: where the GEQRT unit works instead of tile (k,k) and its T factor
+// (the A2 panel's FP64 copy).
 template <int NB, int P, bool PRE>
-LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem, int mode) {
+LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem, int mode, typename Tr<P>::S *akk = nullptr,
+                        typename Tr<P>::S *tkk = nullptr) {
     typedef typename Tr<P>::S S;
     constexpr int PP = (P == PB16) ? P32 : P;  // panel-internal updates stay in the storage precision
     S *Ys = (S *)smem;
@@ -560,7 +563,7 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem, int mode) {
     const int tid = threadIdx.x;
     const int epoch = k + 1;
     const int c0 = b * IB;
-    S *Akk = At + c.toff(k, k);
+    S *Akk = akk ? akk : At + c.toff(k, k);
     const int i0 = mode == QR_REST ? k + 1 : k, i1 = mode == QR_GEQRT ? k + 1 : (int)c.n;
     for (int i = i0; i < i1; ++i) {
         if (b > 0) {  // the trailing update of unit (i, b-1) must be in place
@@ -569,7 +572,7 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem, int mode) {
             if (bail) return;
             fence_acquire();
         }
-        S *Ti = Tf + c.tqoff(i, k);
+        S *Ti = (i == k && tkk) ? tkk : Tf + c.tqoff(i, k);
         if (i == k) {
             panel_qr<NB, S, false>(Akk, c0, nullptr, Ys, Ts, pl);
             for (int e = tid; e < IB * IB; e += WG) Ti[(c0 + e % IB) + (c0 + e / IB) * NB] = Ts[e];
@@ -611,7 +614,7 @@ template <int NB, int P> constexpr int qr_occ() { return qr_step_lds<NB, P>() <=
 
 template <int NB, int P>
 __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k, int mode) {
-    if (mode != QR_GEQRT && c.dec[k] != 0) return;  // the A2 panel's GEQRT runs before the decision
+    if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
     constexpr int VB = qr_vblk<NB>();
@@ -727,6 +730,17 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
         }
         __syncthreads();
     }
+}
+
+// Panel of variant A2 (Sec. 2.3): GEQRT of the FP64 copy W_k of A_kk by the
+// QR step's producers in FP64 (grid nb/IB), T's diagonal blocks into the
+// Dinv_k slot until k_a2_commit; publishes the flags of tile k for the QR
+// step that may continue from it.
+template <int NB>
+__global__ __launch_bounds__(WG) void k_a2_geqrt(Ctx c, int k) {
+    __shared__ __attribute__((aligned(16))) char smem[qr_lds<NB, P64>()];
+    qr_producer<NB, P64, false>(c, k, (int)blockIdx.x, smem, QR_GEQRT, c.W + (size_t)k * NB * NB,
+                                c.Dinv + (size_t)k * NB * NB);
 }
 
 // ---------------------------------------------------------------------------

@@ -517,10 +517,10 @@ template <int MODE> LQ_DEV void fw_rows(FwTile &t, const double *v, int nq, doub
         for (int e = 0; e < 4; ++e) red[(w * nq + q) * 256 + 4 * l + e] = acc[e];
     }
 }
-// The same row products for the FP64 unit-lower L_kk^{-1} (MODE 2), in four
-// passes of 8 columns per wave: lane l holds rows 2l, 2l+1 and 128+2l,
-// 128+2l+1.
-LQ_DEV void fw_rows_linv(const double *M, const double *v, int nq, double *red) {
+// The same row products for the FP64 unit-lower L_kk^{-1} (MODE 2; dense:
+// as stored, for variant A2's Q_kk^T), in four passes of 8 columns per wave:
+// lane l holds rows 2l, 2l+1 and 128+2l, 128+2l+1.
+LQ_DEV void fw_rows_linv(const double *M, const double *v, int nq, double *red, bool dense) {
     const int w = wave_id(), l = lane_id();
     double acc[FW_RQ][4];
 #pragma unroll
@@ -543,7 +543,7 @@ LQ_DEV void fw_rows_linv(const double *M, const double *v, int nq, double *red) 
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int p = 128 * h + 2 * l + e;
-                    const double x = p > cc ? a[j][h][e] : (p == cc ? 1.0 : 0.0);
+                    const double x = (dense || p > cc) ? a[j][h][e] : (p == cc ? 1.0 : 0.0);
 #pragma unroll
                     for (int q = 0; q < FW_RQ; ++q)
                         if (q < nq) acc[q][2 * h + e] += x * v[q * 256 + cc];
@@ -613,7 +613,7 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
         const int *pm = c.perm + (size_t)k * 256;
         for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = ld((int64_t)k * 256 + pm[e % 256] + (int64_t)(q0 + e / 256) * Np);
         __syncthreads();
-        fw_rows_linv(c.Linv + (size_t)k * 256 * 256, yi, nq, red);
+        fw_rows_linv(c.Linv + (size_t)k * 256 * 256, yi, nq, red, c.a2);  // A2: the dense Q_kk^T
         __syncthreads();
         for (int e = tid; e < 256 * nq; e += FW_WG) {
             const int q = e / 256, p = e % 256;

@@ -3,7 +3,8 @@ oracle's A2: decisions outside the 1e-6 band, s_k to 1e-9, the factored
 matrix to 1e-10 of its largest entry and the solution to 1e-10 (FP64); every
 forced sequence of a small ragged matrix; the mixed-precision solve reaching
 the FP64 backward-error target; an all-QR sequence identical to A1's; the
-zero-pivot status; lookahead bit-identical to the ordered run."""
+zero-pivot status; lookahead bit-identical to the ordered run; the wavefront
+forward pass equal to the per-step one."""
 import itertools
 
 import numpy as np
@@ -136,3 +137,22 @@ def test_a2_lookahead_bit_identical(gpu):
     assert np.array_equal(fa.decisions()[0], fb.decisions()[0])
     assert np.array_equal(fa.export()[0].cpu().numpy(), fb.export()[0].cpu().numpy())
     assert np.array_equal(fa.solve(dev(b)).cpu().numpy(), fb.solve(dev(b)).cpu().numpy())
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_wavefront_forward_matches_per_step(gpu, variant):
+    """FP32 at n_b = 256 with at most 16 right-hand sides solves through the
+    one-launch wavefront forward pass; 17 take the per-step kernels.  Both are
+    FP64 arithmetic on the same factors, so the first column agrees to
+    rounding (A2: its LU rows take the dense Q_kk^T)."""
+    import torch
+    N, nb = 1536, 256
+    A = inputs.usv(N, 1e2, seed=(811,))
+    B = inputs.rhs(N, 17, seed=(812,))
+    seq = np.array([1, 0, 1, 1, 0, 1], np.int8)  # both kinds of step, LU after QR and after LU
+    f = gpu.factor(dev(A), nb, criterion="forced", forced=seq, precision="fp32", nrhs_max=17, variant=variant)
+    assert np.array_equal(f.decisions()[0], seq)
+    x1 = f.solve(dev(B[:, :1].copy())).cpu().numpy()[:, 0]
+    x17 = f.solve(dev(B)).cpu().numpy()[:, 0]
+    assert np.linalg.norm(x1 - x17) <= 1e-12 * np.linalg.norm(x17)
+    del torch
