@@ -788,20 +788,29 @@ __global__ __launch_bounds__(WG) void k_a2_qt(Ctx c, int k) {
         }
         Ts[tid] = T[(c0 + tid % IB) + (size_t)(c0 + tid / IB) * NB];  // Ts[q*IB + p] = T(p, q)
         __syncthreads();
-        double w = 0.0;  // W = V_b^T C
-        for (int r = c0 + p; r < NB; ++r) w += Vs[p * NB + r] * C[r * 16 + col];
-        Wb[p * 16 + col] = w;
+        // W = V_b^T C over rows c0.. (V's zeros above its diagonal included),
+        // in four interleaved partial sums
+        double w4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = c0; r < NB; r += 4)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w4[u] += Vs[p * NB + r + u] * C[(r + u) * 16 + col];
+        Wb[p * 16 + col] = (w4[0] + w4[1]) + (w4[2] + w4[3]);
         __syncthreads();
         double wt = 0.0;  // T_b^T W: (T^T)(p, q) = T(q, p), nonzero for q <= p
         for (int q = 0; q <= p; ++q) wt += Ts[p * IB + q] * Wb[q * 16 + col];
         Wt[p * 16 + col] = wt;
         __syncthreads();
-        for (int e = tid; e < NB * 16; e += WG) {  // C -= V_b (T_b^T W)
-            const int r = e / 16, cc = e % 16;
-            if (r < c0) continue;
+        // C -= V_b (T_b^T W); every row this thread updates is in column col
+        // (WG is a multiple of 16), so that column of T_b^T W stays in registers
+        double wc[IB];
+#pragma unroll
+        for (int q = 0; q < IB; ++q) wc[q] = Wt[q * 16 + col];
+        static_assert(IB * 16 % WG == 0, "row c0 starts a whole pass of the workgroup");
+        for (int e = tid + c0 * 16; e < NB * 16; e += WG) {  // rows c0..; above them V_b is zero
+            const int r = e / 16;
             double acc = 0.0;
 #pragma unroll
-            for (int q = 0; q < IB; ++q) acc += Vs[q * NB + r] * Wt[q * 16 + cc];
+            for (int q = 0; q < IB; ++q) acc += Vs[q * NB + r] * wc[q];
             C[e] -= acc;
         }
         __syncthreads();
