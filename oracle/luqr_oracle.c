@@ -29,6 +29,12 @@
  *   Tq     n*n blocks of nb*nb: block (i,k) at Tq + (k*n + i)*nb*nb holds the
  *          upper-triangular compact-WY factor of the reflectors that
  *          eliminated tile (i,k) (TSQRT), or of GEQRT for i == k.
+ *   With an elimination tree (qr_tree = S > 0, oracle_factor_t): the
+ *          heads of the groups of S tiles keep the unit-lower V of their
+ *          GEQRT below the diagonal and Tq(h,k) holds its factor; a head h
+ *          later killed by another head keeps the TTQRT reflector tails
+ *          (upper triangular) on and above its diagonal, and Tt(h,k) (same
+ *          layout as Tq) holds their factor.
  *   ipiv   N ints: for an LU step k, ipiv[k*nb + c] is the local row (0-based
  *          within tile k) exchanged with local row c at column c of GETRF.
  *          QR steps store the identity.
@@ -479,6 +485,86 @@ void oracle_tsmqr(int64_t mk, int64_t mi, const double *Y, int64_t ldy, const do
     free(W);
 }
 
+/* TTQRT (Alg. 4b): QR of [R1; R2] with both m_k x m_k upper triangular.
+ * Reflector c is v_c = [e_c; y_c] with y_c = R2(0..c, c) (zero below row c,
+ * so the tails stay upper triangular and overwrite R2's upper triangle); R1
+ * is updated in place and T is the compact-WY factor of the m_k
+ * reflectors.  Equal to TSQRT on a triangular R2 with the zero products
+ * left out. */
+void oracle_ttqrt(int64_t mk, double *R1, int64_t ld1, double *R2, int64_t ld2, double *T, int64_t ldt)
+{
+    for (int64_t j = 0; j < mk; ++j)
+        for (int64_t i = 0; i < mk; ++i) T[IX(i, j, ldt)] = 0.0;
+    double *w = (double *)malloc((size_t)(mk > 0 ? mk : 1) * sizeof(double));
+    for (int64_t c = 0; c < mk; ++c) {
+        double tau = householder(&R1[IX(c, c, ld1)], &R2[IX(0, c, ld2)], c + 1, 1);
+        for (int64_t j = c + 1; j < mk; ++j) {
+            double s = R1[IX(c, j, ld1)];
+            for (int64_t r = 0; r <= c; ++r) s += R2[IX(r, c, ld2)] * R2[IX(r, j, ld2)];
+            s *= tau;
+            R1[IX(c, j, ld1)] -= s;
+            for (int64_t r = 0; r <= c; ++r) R2[IX(r, j, ld2)] -= R2[IX(r, c, ld2)] * s;
+        }
+        for (int64_t l = 0; l < c; ++l) { /* w_l = y_l^T y_c, y_l zero below row l */
+            double s = 0.0;
+            for (int64_t r = 0; r <= l; ++r) s += R2[IX(r, l, ld2)] * R2[IX(r, c, ld2)];
+            w[l] = s;
+        }
+        for (int64_t l = 0; l < c; ++l) {
+            double s = 0.0;
+            for (int64_t q = l; q < c; ++q) s += T[IX(l, q, ldt)] * w[q];
+            T[IX(l, c, ldt)] = -tau * s;
+        }
+        T[IX(c, c, ldt)] = tau;
+    }
+    free(w);
+}
+
+/* TTMQR: [C1; C2] <- Q^T [C1; C2] for the TTQRT reflectors V = [I; Y], Y
+ * upper triangular (its upper triangle in Y, entries below ignored):
+ * W = T^T (C1 + Y^T C2); C1 -= W; C2 -= Y W. */
+void oracle_ttmqr(int64_t mk, const double *Y, int64_t ldy, const double *T, int64_t ldt,
+                  int64_t nc, double *C1, int64_t ld1, double *C2, int64_t ld2)
+{
+    double *W = (double *)malloc((size_t)(mk > 0 ? mk : 1) * sizeof(double));
+    for (int64_t j = 0; j < nc; ++j) {
+        for (int64_t l = 0; l < mk; ++l) {
+            double s = C1[IX(l, j, ld1)];
+            for (int64_t r = 0; r <= l; ++r) s += Y[IX(r, l, ldy)] * C2[IX(r, j, ld2)];
+            W[l] = s;
+        }
+        for (int64_t l = mk - 1; l >= 0; --l) {
+            double s = 0.0;
+            for (int64_t q = 0; q <= l; ++q) s += T[IX(q, l, ldt)] * W[q];
+            W[l] = s;
+        }
+        for (int64_t l = 0; l < mk; ++l) C1[IX(l, j, ld1)] -= W[l];
+        for (int64_t l = 0; l < mk; ++l)
+            for (int64_t r = 0; r <= l; ++r) C2[IX(r, j, ld2)] -= Y[IX(r, l, ldy)] * W[l];
+    }
+    free(W);
+}
+
+/* The elimination tree of a QR step (Sec. 2.2, Alg. 3; the two-level
+ * reduction of Sec. 2.2 and 4.2): the panel tiles k..n-1 form groups of S
+ * consecutive tiles (S = qr_tree; S <= 0 or S >= n-k: one group, the flat
+ * tree), a trailing group of a single tile joining the group before it.
+ * Within a group its first tile (the head) eliminates the others with TS
+ * kernels (Alg. 4a); then the heads are reduced by a binary tree of TT
+ * kernels (Alg. 4b): at distance d = 1, 2, 4, .., head g eliminates head
+ * g + d for g = 0, 2d, 4d, ...  head[0..G-1] receive the heads, head[G] = n;
+ * returns G. */
+static int64_t qr_groups(int64_t k, int64_t n, int32_t S, int64_t *head)
+{
+    const int64_t m = n - k;
+    const int64_t s = (S <= 0 || S >= m) ? m : S;
+    int64_t G = (m + s - 1) / s;
+    if (G > 1 && m - (G - 1) * s == 1) --G;
+    for (int64_t g = 0; g < G; ++g) head[g] = k + g * s;
+    head[G] = n;
+    return G;
+}
+
 /* LU-step kernels of Alg. 2. */
 /* Eliminate: X <- X U^{-1} (U upper, non-unit), X is mi x mk. */
 static void trsm_right_upper(int64_t mk, const double *U, int64_t ldu, int64_t mi, double *X, int64_t ldx)
@@ -557,12 +643,17 @@ static double step_units(int64_t r, int is_qr) { return step_units_v(r, is_qr, 0
 /*                    continues from the same GEQRT.  A2 is defined for the */
 /*                    Max, Sum, Random and Forced criteria without a domain */
 /*                    or the estimate (-23 otherwise).                      */
-int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
-                     uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
-                     double *B, int64_t ldb, int64_t nrhs,
-                     int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
-                     double *margin_out, double *diag, int32_t domain_stride, int32_t invnorm_estimate,
-                     int32_t lu_variant)
+/*   qr_tree          0: every QR step is the flat TS tree (Alg. 4a, the     */
+/*                    eliminator of every A_ik is A_kk); S > 0: groups of S   */
+/*                    tiles reduced by TS, their heads by a binary TT tree    */
+/*                    (qr_groups); Tt (n*n blocks of nb*nb, required then)    */
+/*                    receives the TT factors.                               */
+int oracle_factor_t(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
+                    uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
+                    double *B, int64_t ldb, int64_t nrhs,
+                    int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
+                    double *margin_out, double *diag, int32_t domain_stride, int32_t invnorm_estimate,
+                    int32_t lu_variant, int32_t qr_tree, double *Tt)
 {
     if (N < 1) return -1;
     if (nb < 1) return -4;
@@ -575,6 +666,8 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
     if (lu_variant < 0 || lu_variant > 2) return -22;
     const int a2 = lu_variant == 2;
     if (a2 && (domain_stride > 0 || invnorm_estimate || criterion == CRIT_MUMPS)) return -23;
+    if (qr_tree < 0) return -24;
+    if (qr_tree > 0 && !Tt) return -25;
 
     const int64_t n = (N + nb - 1) / nb;
     if (nsteps < 0 || nsteps > n) nsteps = n;
@@ -591,6 +684,7 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
     double *Wd = domain_stride > 0 ? (double *)malloc((size_t)N * (size_t)nb * sizeof(double)) : NULL;
     double *Pd = domain_stride > 0 ? (double *)malloc((size_t)N * (size_t)nb * sizeof(double)) : NULL;
     int32_t *dpiv = (int32_t *)calloc((size_t)nb, sizeof(int32_t));
+    int64_t *ghead = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
 
     if (diag) {
         for (int q = 0; q < DG_COUNT; ++q) diag[q] = 0.0;
@@ -830,24 +924,48 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
              * A1: A_kk was never modified (the LU attempt ran on the copy W: restore
              * is a no-op).  A2: the GEQRT of A_kk is the Factor's, kept (Sec. 2.3). */
             if (ipiv) for (int64_t c = 0; c < mk; ++c) ipiv[k * nb + c] = (int32_t)c;
-            if (!a2) oracle_geqrt(mk, Akk, lda, Tkk, nb);
-#pragma omp parallel for schedule(dynamic, 1)
-            for (int64_t j = k + 1; j < n; ++j)
-                oracle_unmqr(mk, Akk, lda, Tkk, nb, tsize(N, nb, j), &A[IX(k * nb, j * nb, lda)], lda);
-            if (B) oracle_unmqr(mk, Akk, lda, Tkk, nb, nrhs, &B[IX(k * nb, 0, ldb)], ldb);
-            for (int64_t i = k + 1; i < n; ++i) {
-                int64_t mi = tsize(N, nb, i);
-                double *Aik = &A[IX(i * nb, k * nb, lda)];
-                double *Tik = Tq ? &Tq[((size_t)k * n + i) * nb * nb] : Tloc;
-                oracle_tsqrt(mk, Akk, lda, mi, Aik, lda, Tik, nb);
+            /* the elimination list of Alg. 3: within each group its head
+             * eliminates the other tiles with TS kernels (Alg. 4a); with one
+             * group (qr_tree = 0) the head is A_kk and this is the flat tree */
+            const int64_t G = qr_groups(k, n, qr_tree, ghead);
+            for (int64_t g = 0; g < G; ++g) {
+                const int64_t h = ghead[g];
+                double *Ah = &A[IX(h * nb, k * nb, lda)];
+                double *Th = (Tq && h != k) ? &Tq[((size_t)k * n + h) * nb * nb] : Tkk;
+                if (!(a2 && h == k)) oracle_geqrt(mk, Ah, lda, Th, nb);
 #pragma omp parallel for schedule(dynamic, 1)
                 for (int64_t j = k + 1; j < n; ++j)
-                    oracle_tsmqr(mk, mi, Aik, lda, Tik, nb, tsize(N, nb, j),
-                                 &A[IX(k * nb, j * nb, lda)], lda, &A[IX(i * nb, j * nb, lda)], lda);
-                if (B)
-                    oracle_tsmqr(mk, mi, Aik, lda, Tik, nb, nrhs, &B[IX(k * nb, 0, ldb)], ldb,
-                                 &B[IX(i * nb, 0, ldb)], ldb);
+                    oracle_unmqr(mk, Ah, lda, Th, nb, tsize(N, nb, j), &A[IX(h * nb, j * nb, lda)], lda);
+                if (B) oracle_unmqr(mk, Ah, lda, Th, nb, nrhs, &B[IX(h * nb, 0, ldb)], ldb);
+                for (int64_t i = h + 1; i < ghead[g + 1]; ++i) {
+                    int64_t mi = tsize(N, nb, i);
+                    double *Aik = &A[IX(i * nb, k * nb, lda)];
+                    double *Tik = Tq ? &Tq[((size_t)k * n + i) * nb * nb] : Tloc;
+                    oracle_tsqrt(mk, Ah, lda, mi, Aik, lda, Tik, nb);
+#pragma omp parallel for schedule(dynamic, 1)
+                    for (int64_t j = k + 1; j < n; ++j)
+                        oracle_tsmqr(mk, mi, Aik, lda, Tik, nb, tsize(N, nb, j),
+                                     &A[IX(h * nb, j * nb, lda)], lda, &A[IX(i * nb, j * nb, lda)], lda);
+                    if (B)
+                        oracle_tsmqr(mk, mi, Aik, lda, Tik, nb, nrhs, &B[IX(h * nb, 0, ldb)], ldb,
+                                     &B[IX(i * nb, 0, ldb)], ldb);
+                }
             }
+            /* the heads by a binary tree of TT kernels (Alg. 4b) */
+            for (int64_t dd = 1; dd < G; dd *= 2)
+                for (int64_t g = 0; g + dd < G; g += 2 * dd) {
+                    const int64_t h0 = ghead[g], h1 = ghead[g + dd];
+                    double *A0 = &A[IX(h0 * nb, k * nb, lda)], *A1 = &A[IX(h1 * nb, k * nb, lda)];
+                    double *T1 = &Tt[((size_t)k * n + h1) * nb * nb];
+                    oracle_ttqrt(mk, A0, lda, A1, lda, T1, nb);
+#pragma omp parallel for schedule(dynamic, 1)
+                    for (int64_t j = k + 1; j < n; ++j)
+                        oracle_ttmqr(mk, A1, lda, T1, nb, tsize(N, nb, j), &A[IX(h0 * nb, j * nb, lda)], lda,
+                                     &A[IX(h1 * nb, j * nb, lda)], lda);
+                    if (B)
+                        oracle_ttmqr(mk, A1, lda, T1, nb, nrhs, &B[IX(h0 * nb, 0, ldb)], ldb,
+                                     &B[IX(h1 * nb, 0, ldb)], ldb);
+                }
         }
         if (diag) diag[DG_TRUEFLOPS] += step_units_v(n - k - 1, !lu, a2) * (double)nb * (double)nb * (double)nb;
     }
@@ -856,8 +974,20 @@ int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t crit
         diag[DG_GROWTH_ELEM] = max_elem0 > 0 ? max_elem / max_elem0 : 0.0;
     }
     free(piv); free(W); free(Tloc); free(colsum_scratch); free(away); free(lmax); free(nrm_before);
-    free(dtile); free(Wd); free(Pd); free(dpiv);
+    free(dtile); free(Wd); free(Pd); free(dpiv); free(ghead);
     return 0;
+}
+
+int oracle_factor_ex(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
+                     uint64_t seed, const int8_t *forced, int32_t mumps_reading, int64_t nsteps,
+                     double *B, int64_t ldb, int64_t nrhs,
+                     int32_t *ipiv, double *Tq, int8_t *dec, double *s_out, double *m_out,
+                     double *margin_out, double *diag, int32_t domain_stride, int32_t invnorm_estimate,
+                     int32_t lu_variant)
+{
+    return oracle_factor_t(N, A, lda, nb, criterion, alpha, seed, forced, mumps_reading, nsteps, B, ldb, nrhs,
+                           ipiv, Tq, dec, s_out, m_out, margin_out, diag, domain_stride, invnorm_estimate,
+                           lu_variant, 0, NULL);
 }
 
 int oracle_factor_domain(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criterion, double alpha,
@@ -886,14 +1016,16 @@ int oracle_factor(int64_t N, double *A, int64_t lda, int64_t nb, int32_t criteri
 /* Tq, dec are oracle_factor outputs of a full factorization.              */
 /* ---------------------------------------------------------------------- */
 /* lu_variant 2: an LU step replays Q_kk^T (from V_kk and Tq(k,k)) on B_k
- * before the block eliminations below it (Sec. 2.3). */
-void oracle_forward_v(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+ * before the block eliminations below it (Sec. 2.3).  qr_tree, Tt: a QR step
+ * replays its elimination tree (qr_groups) in the factorization's order. */
+void oracle_forward_t(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
                       const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
-                      int32_t domain_stride, int32_t lu_variant)
+                      int32_t domain_stride, int32_t lu_variant, int32_t qr_tree, const double *Tt)
 {
     const int64_t n = (N + nb - 1) / nb;
     int64_t *dtile = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     int32_t *ident = (int32_t *)malloc((size_t)nb * sizeof(int32_t));
+    int64_t *ghead = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
     for (int64_t c = 0; c < nb; ++c) ident[c] = (int32_t)c;
     for (int64_t k = 0; k < n; ++k) {
         const int64_t mk = tsize(N, nb, k);
@@ -920,13 +1052,32 @@ void oracle_forward_v(int64_t N, const double *F, int64_t ldf, int64_t nb, const
                 gemm_minus(tsize(N, nb, i), nrhs, mk, &F[IX(i * nb, k * nb, ldf)], ldf, Bk, ldb,
                            &B[IX(i * nb, 0, ldb)], ldb);
         } else {
-            oracle_unmqr(mk, Fkk, ldf, &Tq[((size_t)k * n + k) * nb * nb], nb, nrhs, Bk, ldb);
-            for (int64_t i = k + 1; i < n; ++i)
-                oracle_tsmqr(mk, tsize(N, nb, i), &F[IX(i * nb, k * nb, ldf)], ldf,
-                             &Tq[((size_t)k * n + i) * nb * nb], nb, nrhs, Bk, ldb, &B[IX(i * nb, 0, ldb)], ldb);
+            const int64_t G = qr_groups(k, n, qr_tree, ghead);
+            for (int64_t g = 0; g < G; ++g) {
+                const int64_t h = ghead[g];
+                const double *Fh = &F[IX(h * nb, k * nb, ldf)];
+                double *Bh = &B[IX(h * nb, 0, ldb)];
+                oracle_unmqr(mk, Fh, ldf, &Tq[((size_t)k * n + h) * nb * nb], nb, nrhs, Bh, ldb);
+                for (int64_t i = h + 1; i < ghead[g + 1]; ++i)
+                    oracle_tsmqr(mk, tsize(N, nb, i), &F[IX(i * nb, k * nb, ldf)], ldf,
+                                 &Tq[((size_t)k * n + i) * nb * nb], nb, nrhs, Bh, ldb, &B[IX(i * nb, 0, ldb)], ldb);
+            }
+            for (int64_t dd = 1; dd < G; dd *= 2)
+                for (int64_t g = 0; g + dd < G; g += 2 * dd) {
+                    const int64_t h0 = ghead[g], h1 = ghead[g + dd];
+                    oracle_ttmqr(mk, &F[IX(h1 * nb, k * nb, ldf)], ldf, &Tt[((size_t)k * n + h1) * nb * nb], nb, nrhs,
+                                 &B[IX(h0 * nb, 0, ldb)], ldb, &B[IX(h1 * nb, 0, ldb)], ldb);
+                }
         }
     }
-    free(dtile); free(ident);
+    free(dtile); free(ident); free(ghead);
+}
+
+void oracle_forward_v(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+                      const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
+                      int32_t domain_stride, int32_t lu_variant)
+{
+    oracle_forward_t(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs, domain_stride, lu_variant, 0, NULL);
 }
 
 void oracle_forward_domain(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
@@ -980,6 +1131,14 @@ void oracle_solve_v(int64_t N, const double *F, int64_t ldf, int64_t nb, const i
                     int32_t domain_stride, int32_t lu_variant)
 {
     oracle_forward_v(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs, domain_stride, lu_variant);
+    oracle_backward(N, F, ldf, nb, B, ldb, nrhs);
+}
+
+void oracle_solve_t(int64_t N, const double *F, int64_t ldf, int64_t nb, const int32_t *ipiv,
+                    const double *Tq, const int8_t *dec, double *B, int64_t ldb, int64_t nrhs,
+                    int32_t domain_stride, int32_t lu_variant, int32_t qr_tree, const double *Tt)
+{
+    oracle_forward_t(N, F, ldf, nb, ipiv, Tq, dec, B, ldb, nrhs, domain_stride, lu_variant, qr_tree, Tt);
     oracle_backward(N, F, ldf, nb, B, ldb, nrhs);
 }
 

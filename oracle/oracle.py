@@ -61,6 +61,17 @@ def lib():
         L.oracle_factor_ex.restype = C.c_int
         L.oracle_factor_ex.argtypes = [i64, dp, i64, i64, i32, f64, C.c_uint64, bp, i32, i64,
                                        dp, i64, i64, ip, dp, bp, dp, dp, dp, dp, i32, i32, i32]
+        L.oracle_factor_t.restype = C.c_int
+        L.oracle_factor_t.argtypes = [i64, dp, i64, i64, i32, f64, C.c_uint64, bp, i32, i64,
+                                      dp, i64, i64, ip, dp, bp, dp, dp, dp, dp, i32, i32, i32, i32, dp]
+        L.oracle_solve_t.restype = None
+        L.oracle_solve_t.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64, i32, i32, i32, dp]
+        L.oracle_forward_t.restype = None
+        L.oracle_forward_t.argtypes = [i64, dp, i64, i64, ip, dp, bp, dp, i64, i64, i32, i32, i32, dp]
+        L.oracle_ttqrt.restype = None
+        L.oracle_ttqrt.argtypes = [i64, dp, i64, dp, i64, dp, i64]
+        L.oracle_ttmqr.restype = None
+        L.oracle_ttmqr.argtypes = [i64, dp, i64, dp, i64, i64, dp, i64, dp, i64]
         L.oracle_inv_norm1_qr.restype = f64
         L.oracle_inv_norm1_qr.argtypes = [i64, dp, i64, dp, i64]
         L.oracle_solve_v.restype = None
@@ -136,6 +147,8 @@ class OracleFactors:
     Bt: np.ndarray | None = None   # forward-transformed B in augmented mode
     domain: int = 0          # stride p of the diagonal domain (0: the diagonal tile alone)
     variant: int = 1         # LU-step variant: 1 = A1 (Alg. 2), 2 = A2 (Sec. 2.3)
+    tree: int = 0            # QR elimination tree: 0 flat TS; S > 0 TS groups of S, TT tree over their heads
+    Tt: np.ndarray | None = None  # TT factors of the killed heads (tree > 0)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -147,14 +160,16 @@ class OracleFactors:
 
 
 def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading=0,
-           nsteps=-1, B=None, domain=0, estimate=False, variant=1) -> OracleFactors:
+           nsteps=-1, B=None, domain=0, estimate=False, variant=1, tree=0) -> OracleFactors:
     """Hybrid LU-QR factorization (Alg. 1) of a copy of A.  domain = p > 0
     pivots the LU attempt over the diagonal domain (the panel tiles k, k+p,
     k+2p, ...; Sec. 2.1), domain = 0 within the diagonal tile.  estimate:
     the criteria take ||A_kk^{-1}||_1 from the O(n_b^2) iterative estimate
     (Sec. 3.4) instead of computing it exactly.  variant: the LU step, 1 =
     A1 (GEPP on a backup of A_kk, Alg. 2), 2 = A2 (GEQRT of A_kk first, kept
-    by a QR step; Sec. 2.3)."""
+    by a QR step; Sec. 2.3).  tree: the QR steps' elimination tree, 0 = flat
+    TS (Alg. 4a), S > 0 = TS within groups of S tiles and a binary TT tree over
+    the groups' heads (Alg. 3, 4a/4b; Sec. 2.2)."""
     A = _fortran(A)
     N = A.shape[0]
     assert A.shape == (N, N)
@@ -176,11 +191,12 @@ def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading
     if B is not None:
         Bt = _fortran(B.reshape(N, -1) if B.ndim == 1 else B)
         nrhs = Bt.shape[1]
-    if estimate or variant != 1:
-        rc = lib().oracle_factor_ex(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
-                                    int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
-                                    _b(dec), _d(s), _d(m), _d(margin), _d(diag), int(domain),
-                                    1 if estimate else 0, int(variant))
+    Tt = np.zeros(n * n * nb * nb, dtype=np.float64) if tree else None
+    if estimate or variant != 1 or tree:
+        rc = lib().oracle_factor_t(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
+                                   int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
+                                   _b(dec), _d(s), _d(m), _d(margin), _d(diag), int(domain),
+                                   1 if estimate else 0, int(variant), int(tree), _d(Tt))
     elif domain:
         rc = lib().oracle_factor_domain(N, _d(A), N, nb, crit, float(alpha), C.c_uint64(seed), _b(f),
                                         int(mumps_reading), int(nsteps), _d(Bt), N, nrhs, _i(ipiv), _d(Tq),
@@ -191,7 +207,7 @@ def factor(A, nb, criterion="max", alpha=1.0, seed=0, forced=None, mumps_reading
                                  _b(dec), _d(s), _d(m), _d(margin), _d(diag))
     if rc != 0:
         raise ValueError(f"oracle_factor rejected argument {-rc}")
-    return OracleFactors(N, nb, A, ipiv, Tq, dec, s, m, margin, diag, Bt, int(domain), int(variant))
+    return OracleFactors(N, nb, A, ipiv, Tq, dec, s, m, margin, diag, Bt, int(domain), int(variant), int(tree), Tt)
 
 
 def solve(fac: OracleFactors, B):
@@ -199,7 +215,10 @@ def solve(fac: OracleFactors, B):
     B = np.asarray(B, dtype=np.float64)
     vec = B.ndim == 1
     X = _fortran(B.reshape(fac.N, -1))
-    if fac.variant == 2:
+    if fac.tree:
+        lib().oracle_solve_t(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
+                             _d(X), fac.N, X.shape[1], fac.domain, fac.variant, fac.tree, _d(fac.Tt))
+    elif fac.variant == 2:
         lib().oracle_solve_v(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
                              _d(X), fac.N, X.shape[1], fac.domain, 2)
     elif fac.domain:
@@ -213,8 +232,8 @@ def solve(fac: OracleFactors, B):
 
 def forward(fac: OracleFactors, B):
     X = _fortran(np.asarray(B, dtype=np.float64).reshape(fac.N, -1))
-    lib().oracle_forward_v(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
-                           _d(X), fac.N, X.shape[1], fac.domain, fac.variant)
+    lib().oracle_forward_t(fac.N, _d(fac.F), fac.N, fac.nb, _i(fac.ipiv), _d(fac.Tq), _b(fac.dec),
+                           _d(X), fac.N, X.shape[1], fac.domain, fac.variant, fac.tree, _d(fac.Tt))
     return X
 
 
@@ -292,6 +311,27 @@ def tsmqr(Y, T, Ck, Ci):
     lib().oracle_tsmqr(Ck.shape[0], Ci.shape[0], _d(Y), Y.shape[0], _d(T), T.shape[0], Ck.shape[1],
                        _d(Ck), Ck.shape[0], _d(Ci), Ci.shape[0])
     return Ck, Ci
+
+
+def ttqrt(R1, R2):
+    """TTQRT of two upper-triangular tiles (Alg. 4b): returns R1', the tails Y
+    (upper triangle of R2'), T."""
+    R1 = _fortran(R1)
+    R2 = _fortran(R2)
+    m = R1.shape[0]
+    T = np.zeros((m, m), order="F")
+    lib().oracle_ttqrt(m, _d(R1), m, _d(R2), m, _d(T), m)
+    return R1, R2, T
+
+
+def ttmqr(Y, T, C1, C2):
+    Y = _fortran(Y)
+    T = _fortran(T)
+    C1 = _fortran(C1)
+    C2 = _fortran(C2)
+    m = Y.shape[0]
+    lib().oracle_ttmqr(m, _d(Y), m, _d(T), m, C1.shape[1], _d(C1), m, _d(C2), m)
+    return C1, C2
 
 
 def splitmix64(seed, k):
