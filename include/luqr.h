@@ -112,6 +112,17 @@ typedef struct {
                             are the identity.  With Max, Sum, Random and Forced only,
                             without a domain or the estimate (else LUQR_ERR_UNSUPPORTED);
                             not by the batched entry points. */
+    int32_t qr_tree;     /* QR steps' elimination tree (Sec. 2.2, Alg. 3 and 4).  0 (default):
+                            the flat tree, A_kk eliminates every A_ik with TS kernels (Alg. 4a).
+                            S > 0: the panel tiles k..n-1 form groups of S consecutive tiles
+                            (a last group of one tile joins the group before it); each
+                            group's first tile eliminates the others with TS kernels, and the
+                            groups' first tiles are then reduced by a binary tree of TT
+                            kernels (Alg. 4b): at distance d = 1, 2, 4, .. group g eliminates
+                            group g+d for g = 0, 2d, ..  S = 1 is the binary TT tree; S >= n
+                            is the flat tree.  The tree changes the factors and so the later
+                            decisions; the workspace grows by one T factor per panel tile.
+                            Not by the batched entry points. */
 } luqr_opts;
 
 /* Device-side numerical status, read back by luqr_get_status. */

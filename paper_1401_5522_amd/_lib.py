@@ -30,7 +30,7 @@ class luqr_opts(C.Structure):
                 ("precision", C.c_int32), ("nrhs_max", C.c_int32), ("seed", C.c_uint64),
                 ("forced", C.POINTER(C.c_int8)), ("nsteps", C.c_int32),
                 ("timing", C.c_int32), ("no_lookahead", C.c_int32), ("domain_stride", C.c_int32),
-                ("invnorm_estimate", C.c_int32), ("lu_variant", C.c_int32)]
+                ("invnorm_estimate", C.c_int32), ("lu_variant", C.c_int32), ("qr_tree", C.c_int32)]
 
 
 class luqr_status(C.Structure):
@@ -109,7 +109,7 @@ def lib() -> C.CDLL:
 
 
 def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed=0, forced=None,
-              nsteps=-1, timing=False, lookahead=True, domain=0, estimate=False, variant=1):
+              nsteps=-1, timing=False, lookahead=True, domain=0, estimate=False, variant=1, tree=0):
     o = luqr_opts()
     o.nb = int(nb)
     o.criterion = CRITERIA[criterion] if isinstance(criterion, str) else int(criterion)
@@ -127,6 +127,7 @@ def make_opts(nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed
     o.domain_stride = int(domain)
     o.invnorm_estimate = 1 if estimate else 0
     o.lu_variant = int(variant)
+    o.qr_tree = int(tree)
     return o, keep
 
 

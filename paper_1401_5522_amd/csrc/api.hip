@@ -65,6 +65,7 @@ static int check_opts(int64_t N, const luqr_opts *o, int pos_opts) {
     if (o->domain_stride < 0) return -pos_opts;
     if (o->invnorm_estimate < 0 || o->invnorm_estimate > 1) return -pos_opts;
     if (o->lu_variant < 0 || o->lu_variant > 2) return -pos_opts;
+    if (o->qr_tree < 0) return -pos_opts;
     if (o->lu_variant == 2 && (o->criterion == LUQR_CRIT_MUMPS || o->domain_stride > 0 || o->invnorm_estimate))
         return LUQR_ERR_UNSUPPORTED;  // A2 has no GEPP pivots, domain or triangular L^-1 for these
     if (!pick_ops(o->nb, o->precision)) return LUQR_ERR_UNSUPPORTED;
@@ -79,7 +80,7 @@ extern "C" int64_t luqr_workspace_bytes(int64_t N, const luqr_opts *o) {
     if (N < 1) return -1;
     int rc = check_opts(N, o, 2);
     if (rc) return rc;
-    Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride);
+    Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride, o->qr_tree);
     return (int64_t)L.total;
 }
 
@@ -93,7 +94,7 @@ extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_
     if (rc) return rc;
     if (!dWork || ((uintptr_t)dWork & 255)) return -5;
     if (!out) return -8;
-    Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride);
+    Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride, o->qr_tree);
     if (work_bytes < (int64_t)L.total) return -6;
     luqr_factors_s *f = new (std::nothrow) luqr_factors_s;
     if (!f) return LUQR_ERR_HIP - (int)hipErrorOutOfMemory;
@@ -527,7 +528,7 @@ extern "C" int luqr_solve_noalloc(int64_t N, const double *dA, int64_t lda, cons
     if (!dX) return -8;
     if (ldx < N) return -9;
     if (max_iter < 0) return -10;
-    const Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride);
+    const Layout L = make_layout(N, o->nb, o->precision, o->nrhs_max, o->domain_stride, o->qr_tree);
     if (o->nsteps >= 0 && o->nsteps < L.n) return -4;   // a partial factorization cannot be solved with
     if (L.total > (size_t)LUQR_NOALLOC_SCRATCH_BYTES || L.n > NOALLOC_MAX_STEPS) return LUQR_ERR_TOO_LARGE;
     void *base = nullptr;

@@ -644,6 +644,7 @@ extern "C" int luqr_batched_plan(int64_t batch, const int64_t *N, const int32_t 
     if (o->domain_stride != 0) return LUQR_ERR_UNSUPPORTED;  // each system pivots within its diagonal tiles
     if (o->invnorm_estimate != 0) return LUQR_ERR_UNSUPPORTED;  // the batched kernel takes the exact inverse norm
     if (o->lu_variant == 2) return LUQR_ERR_UNSUPPORTED;  // the batched kernel's LU steps are variant A1
+    if (o->qr_tree != 0) return LUQR_ERR_UNSUPPORTED;     // and its QR steps the flat tree
     if (!(o->alpha >= 0.0)) return -7;
     std::vector<BSys> v;
     int nm = 0;

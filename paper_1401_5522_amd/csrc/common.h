@@ -243,7 +243,8 @@ struct Layout {
     int prec, nrhs_max;
     int dstride;     // diagonal domain: tiles k, k+dstride, ... of the panel (0: the tile alone)
     int64_t DR;      // rows of the largest stacked domain (nb without a domain)
-    size_t off_WD, off_dperm;
+    int qtree;       // QR elimination tree: group size S (0: the flat tree)
+    size_t off_WD, off_dperm, off_Tt;
     int64_t sz_S;  // bytes of a storage element
     size_t off_At, off_Tf, off_gram, off_W, off_Linv, off_Dinv, off_ipiv, off_perm, off_zpiv;
     size_t off_dec, off_s, off_m, off_margin, off_status;
@@ -256,11 +257,12 @@ struct Layout {
 
 LQ_HD size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max, int dstride = 0) {
+inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max, int dstride = 0, int qtree = 0) {
     Layout L;
     L.N = N; L.nb = nb; L.n = (N + nb - 1) / nb; L.Np = L.n * nb;
     L.prec = prec; L.nrhs_max = nrhs_max < 1 ? 1 : nrhs_max;
     L.dstride = dstride;
+    L.qtree = qtree;
     L.DR = (dstride > 0 ? 1 + (L.n - 1) / dstride : 1) * nb;
     L.sz_S = prec == P64 ? 8 : 4;
     const size_t n = L.n, b = nb, t2 = b * b;
@@ -268,6 +270,7 @@ inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max, int dst
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     L.off_At = take(n * n * t2 * L.sz_S);
     L.off_Tf = take(n * (n + 1) / 2 * t2 * L.sz_S);
+    L.off_Tt = take(qtree > 0 ? n * (n + 1) / 2 * t2 * L.sz_S : 8);  // TT factors of the killed heads
     L.off_gram = take(n * t2 * 8);
     L.off_W = take(n * t2 * 8);
     L.off_Linv = take(n * t2 * 8);
@@ -336,6 +339,8 @@ struct Ctx {
     int nb;
     int dstride, DR;
     int a2;          // LU steps of variant A2 (GEQRT of A_kk first; Linv holds Q_kk^T, perm the identity)
+    int qtree;       // QR elimination tree: group size S, 0 = flat (see QrTree)
+    void *Tt;        // TT factor of every killed head (i,k) of a tree, laid out as Tf
     // tiles in the diagonal domain of step k, and whether tile row i > k is one of them
     LQ_HD int dcount(int64_t k) const { return 1 + (dstride > 0 ? (int)((n - 1 - k) / dstride) : 0); }
     LQ_HD bool indom(int64_t k, int64_t i) const { return dstride > 0 && i > k && (i - k) % dstride == 0; }
@@ -344,6 +349,33 @@ struct Ctx {
     LQ_HD int64_t tqoff(int64_t i, int64_t k) const { return (k * n - k * (k - 1) / 2 + (i - k)) * (int64_t)nb * nb; }
     LQ_HD int msize(int64_t k) const { return (int)((k < n - 1) ? nb : N - (n - 1) * (int64_t)nb); }
 };
+
+// The elimination tree of QR step k (Sec. 2.2, Alg. 3; the two-level
+// reduction of Sec. 2.2 and 4.2): the panel tiles k..n-1 in groups of s
+// consecutive tiles (s = S, or all of them for S = 0 or S >= n-k: the flat
+// tree), a last group of a single tile joining the group before it.  Within
+// a group its first tile (the head) eliminates the others with TS kernels
+// (Alg. 4a); the heads are then reduced by a binary tree of TT kernels (Alg.
+// 4b): at distance d = 1, 2, 4, .. head g eliminates head g+d for g = 0, 2d,
+// 4d, ..  Every head but tile k is eliminated exactly once.
+struct QrTree {
+    int k, n, s, G;
+    LQ_HD QrTree(int64_t n_, int64_t k_, int S) : k((int)k_), n((int)n_) {
+        const int m = n - k;
+        s = (S <= 0 || S >= m) ? m : S;
+        G = (m + s - 1) / s;
+        if (G > 1 && m - (G - 1) * s == 1) --G;
+    }
+    LQ_HD int head(int g) const { return k + g * s; }
+    LQ_HD int end(int g) const { return g + 1 < G ? k + (g + 1) * s : n; }
+    LQ_HD bool is_head(int i) const { return (i - k) % s == 0 && (i - k) / s < G; }
+    LQ_HD int npairs(int d) const { return G > d ? (G - d - 1) / (2 * d) + 1 : 0; }
+    LQ_HD static int level(int d) { int l = 1; while (d > 1) { d >>= 1; ++l; } return l; }
+};
+
+// Flag value of step k's launches: 16 per step, phase 0 for the groups (and
+// the A2 panel's GEQRT), 1 + log2(d) for the TT level at distance d.
+LQ_HD int qr_epoch(int k, int phase) { return (k + 1) * 16 + phase; }
 
 inline Ctx make_ctx(const Layout &L, void *base, int a2 = 0) {
     char *b = (char *)base;
@@ -360,6 +392,8 @@ inline Ctx make_ctx(const Layout &L, void *base, int a2 = 0) {
     c.N = L.N; c.n = L.n; c.nb = (int)L.nb;
     c.dstride = L.dstride; c.DR = (int)L.DR;
     c.a2 = a2;
+    c.qtree = L.qtree;
+    c.Tt = b + L.off_Tt;
     return c;
 }
 

@@ -92,7 +92,13 @@ struct Eng {
                 k_lu_update<NB, P><<<(unsigned)rest * cols * PER * PER, WG, 0, st>>>(c, k, k + 1);
             }
             if (ev) (void)hipEventRecord(ev[E * k + 3], st);
-            k_qr_step<NB, P><<<qr_pw<NB>() + rest * qr_spc<NB>(), WG, 0, st>>>(c, k, c.a2 ? QR_REST : QR_FULL);
+            {  // the groups' chains, then the TT levels of the elimination tree
+                const QrTree tr(n, k, c.qtree);
+                const int mode = c.a2 ? QR_REST : QR_FULL;
+                const unsigned per = qr_pw<NB>() + rest * qr_spc<NB>();
+                k_qr_step<NB, P><<<tr.G * per, WG, 0, st>>>(c, k, mode, 0);
+                for (int d = 1; d < tr.G; d *= 2) k_qr_step<NB, P><<<tr.npairs(d) * per, WG, 0, st>>>(c, k, mode, d);
+            }
             if (ev) (void)hipEventRecord(ev[E * k + 4], st);
             hipStream_t sb = st;
             if (side) {
@@ -104,8 +110,12 @@ struct Eng {
             // QR steps: R_kk after every TSQRT (A2's panel inverted the GEQRT's R for the criterion)
             k_qr_rinv<NB, S><<<NB / 4, WG, 0, sb>>>(c, k);
             if constexpr (NB > IB) {
-                k_qr_gram<NB, P><<<dim3(qr_npairs<NB>(), n - k), WG, 0, sb>>>(c, k);
-                k_qr_tfull<NB, P><<<n - k, WG, 0, sb>>>(c, k);
+                k_qr_gram<NB, P><<<dim3(qr_npairs<NB>(), n - k), WG, 0, sb>>>(c, k, 0);
+                k_qr_tfull<NB, P><<<n - k, WG, 0, sb>>>(c, k, 0);
+                if (c.qtree > 0 && QrTree(n, k, c.qtree).G > 1) {  // the TT factors of the killed heads
+                    k_qr_gram<NB, P><<<dim3(qr_npairs<NB>(), n - k), WG, 0, sb>>>(c, k, 1);
+                    k_qr_tfull<NB, P><<<n - k, WG, 0, sb>>>(c, k, 1);
+                }
             }
             if (side) (void)hipEventRecord(side->eb, sb);
             if (ev) (void)hipEventRecord(ev[E * k + 5], sb);
@@ -124,7 +134,7 @@ struct Eng {
             // the forward pass as one wavefront launch; the tile counters reuse
             // the QR steps' flags (n * nb/IB ints, free once the factorization is done)
             const int wch = (s.nrhs + FW_RQ - 1) / FW_RQ;
-            if (c.dstride == 0 && wch <= 4) {
+            if (c.dstride == 0 && c.qtree == 0 && wch <= 4) {  // its QR rows follow the flat tree
                 k_fill_int<<<nblk((int64_t)n * wch), WG, 0, st>>>(c.flags, (int64_t)n * wch, 0);
                 k_fwd_wave<NB, S><<<dim3(n, wch), FW_WG, 0, st>>>(c, s, c.flags);
                 wave = true;
@@ -137,9 +147,14 @@ struct Eng {
                 k_fwd_lu_a<NB><<<dim3(RPT, ch), WG, 0, st>>>(c, s, k);
                 if (rest > 0) k_fwd_lu_b<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
             } else {
+                const QrTree tr(n, k, c.qtree);
                 if (rest > 0) k_fwd_qr_g<NB, S><<<dim3(rest * qs<NB>(), ch), WG, 0, st>>>(c, s, k);
-                k_fwd_qr_chain<NB, S><<<dim3(1, ch), chain_wg<NB, S>(), 0, st>>>(c, s, k);
+                k_fwd_qr_chain<NB, S><<<dim3(tr.G, ch), chain_wg<NB, S>(), 0, st>>>(c, s, k);
                 if (rest > 0) k_fwd_qr_u<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
+                if (c.qtree > 0) {
+                    for (int d = 1; d < tr.G; d *= 2) k_fwd_tt<NB, S><<<dim3(tr.npairs(d), ch), WG, 0, st>>>(c, s, k, d);
+                    k_fwd_tt_fin<NB><<<nblk((int64_t)NB * s.nrhs), WG, 0, st>>>(c, s, k);
+                }
             }
         }
         for (int k = n - 1; k >= 0; --k) {

@@ -216,8 +216,13 @@ LQ_DEV void qr_columns(S (&P)[qr_rpt<NB>()][IB], int c0, S *Rb, S *Ts, PanelLds 
 // entries 2^-60 below the block's largest one can underflow, which is far
 // below the storage rounding of the block (Householder QR is normwise
 // backward stable).
-template <int NB, class S, bool TS>
+// TT (with TS): the bottom tile is upper triangular (TTQRT of Alg. 4b): only
+// its entries on and above the diagonal are read and written, the rest are
+// zeros of the computation (the tile keeps other data there), and the
+// reflector tails come out upper triangular.
+template <int NB, class S, bool TS, bool TT = false>
 LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
+    static_assert(TS || !TT, "a TT panel is a TS panel on a triangular tile");
     constexpr int RPT = qr_rpt<NB>();
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
     S P[RPT][IB];
@@ -227,7 +232,7 @@ LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
         const int r = tid + 256 * u;
 #pragma unroll
         for (int q = 0; q < IB; ++q) {
-            P[u][q] = (r < NB && (TS || r >= c0)) ? A[r + (c0 + q) * NB] : (S)0;
+            P[u][q] = (r < NB && (TS || r >= c0) && (!TT || r <= c0 + q)) ? A[r + (c0 + q) * NB] : (S)0;
             mx = fmax(mx, fabs((double)P[u][q]));
         }
     }
@@ -265,7 +270,7 @@ LQ_DEV void panel_qr(S *A, int c0, S *Rb, S *Ys, S *Ts, PanelLds *pl) {
         if (r >= NB) continue;
 #pragma unroll
         for (int q = 0; q < IB; ++q) {
-            if (TS || r >= c0) A[r + (c0 + q) * NB] = P[u][q];
+            if ((TS || r >= c0) && (!TT || r <= c0 + q)) A[r + (c0 + q) * NB] = P[u][q];
             S v;
             if (TS) v = P[u][q];
             else v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : P[u][q]);
@@ -449,8 +454,7 @@ LQ_DEV void apply_block(typename Tr<P>::acc (&bot)[NB / 16], typename Tr<P>::S *
 // block can be in flight while the current one is applied:
 //   stage_load:  V(:, c0..c0+IB) and T(c0.., c0..) into registers;
 //   stage_store: into LDS, both copies of V(:, c0..c0+IB) and Ts[q*IB + p] = T(p, q);
-//                GEQRT = true makes V unit-lower explicit (zeros above, ones on
-//                the diagonal).
+//                VM selects how V is held in the tile (below).
 template <int NB, class S> struct StageRegs {
     static constexpr int PY = NB * IB / WG, PT = IB * IB / WG;
     static_assert(PY * WG == NB * IB && PT * WG == IB * IB, "whole elements per thread");
@@ -472,14 +476,18 @@ LQ_DEV void stage_load(const S *V, const S *T, int c0, StageRegs<NB, S> &sr) {
     }
 }
 
-template <int NB, class S, bool GEQRT>
+// VM: how V is held in the tile: 0 (TS) as stored; 1 (GEQRT) unit lower,
+// zeros above and ones on the diagonal made explicit; 2 (TT) upper triangular,
+// the entries below the diagonal (another reflector set) read as zeros.
+template <int NB, class S, int VM>
 LQ_DEV void stage_store(const StageRegs<NB, S> &sr, int c0, S *Ys, S *Ts) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int u = 0; u < StageRegs<NB, S>::PY; ++u) {
         const int e = tid + WG * u, r = e % NB, q = e / NB;
         S v = sr.y[u];
-        if (GEQRT) v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : v);
+        if (VM == 1) v = r < c0 + q ? (S)0 : (r == c0 + q ? (S)1 : v);
+        if (VM == 2) v = r <= c0 + q ? v : (S)0;
         put_v<NB>(Ys, r, q, v);
     }
 #pragma unroll
@@ -489,16 +497,16 @@ LQ_DEV void stage_store(const StageRegs<NB, S> &sr, int c0, S *Ys, S *Ts) {
     }
 }
 
-template <int NB, class S, bool GEQRT>
+template <int NB, class S, int VM>
 LQ_DEV void stage_block(const S *V, const S *T, int c0, S *Ys, S *Ts) {
     StageRegs<NB, S> sr;
     stage_load<NB, S>(V, T, c0, sr);
-    stage_store<NB, S, GEQRT>(sr, c0, Ys, Ts);
+    stage_store<NB, S, VM>(sr, c0, Ys, Ts);
 }
 
 // Trailing update of a producer panel: columns (b+1)*IB..NB-1 of A (and, for
 // TS, rows b*IB..b*IB+IB of R) in 64-column strips, with the consumer routine.
-template <int NB, int P, bool TS, bool PRE = true>
+template <int NB, int P, bool TS, bool PRE = true, bool TT = false>
 LQ_DEV void panel_trailing(typename Tr<P>::S *A, typename Tr<P>::S *R, int b, const typename Tr<P>::S *Ys,
                            const typename Tr<P>::S *Ts) {
     typedef typename Tr<P>::S S;
@@ -511,7 +519,10 @@ LQ_DEV void panel_trailing(typename Tr<P>::S *A, typename Tr<P>::S *R, int b, co
 #pragma unroll
         for (int rb = 0; rb < NB / 16; ++rb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) bot[rb][r] = A[(16 * rb + Tr<P>::drow(g, r)) + (col + i16) * NB];
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rb + Tr<P>::drow(g, r);
+                bot[rb][r] = (!TT || row <= col + i16) ? A[row + (col + i16) * NB] : (S)0;  // TT: upper part only
+            }
         apply_block<NB, P, TS, PRE>(bot, TS ? R + (col + i16) * NB : nullptr, b, Ys, Ts);
         // GEQRT: rows above the block are untouched by its reflectors and belong
         // to R row blocks other producers are updating: write back rows >= c0 only
@@ -520,7 +531,7 @@ LQ_DEV void panel_trailing(typename Tr<P>::S *A, typename Tr<P>::S *R, int b, co
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * rb + Tr<P>::drow(g, r);
-                if (TS || row >= b * IB) A[row + (col + i16) * NB] = (S)bot[rb][r];
+                if ((TS || row >= b * IB) && (!TT || row <= col + i16)) A[row + (col + i16) * NB] = (S)bot[rb][r];
             }
     }
 }
@@ -537,20 +548,46 @@ template <int NB> constexpr int qr_pw() { return NB / IB; }  // producer workgro
 
 LQ_DEV int *qr_flag(const Ctx &c, int i, int b) { return &c.flags[(size_t)i * (c.nb / IB) + b]; }
 
-// What the producers of one launch run.  Variant A2 (Sec. 2.3) splits a step
-// at its GEQRT: the panel factors A_kk before the decision (QR_GEQRT: unit
-// i = k only, k_a2_geqrt; it publishes the flags of tile k), and a QR step
-// then continues from it (QR_REST: producers from i = k+1, consumers as in
-// QR_FULL, their UNMQR blocks waiting on the flags already set).
-enum QrMode { QR_FULL = 0, QR_GEQRT = 1, QR_REST = 2 };
+// One chain of a QR-step launch: the top tile row eliminates tile rows
+// mfirst..end-1 of tile column k in order, with TS kernels (Alg. 4a), or, for
+// a killed head of the elimination tree, with TT kernels on its upper
+// triangle (tt; Alg. 4b).  geqrt: the top tile is factored first (GEQRT) and
+// its own row gets the UNMQR blocks.  Launch 0 of a step holds one chain per
+// group of the tree (the whole panel for the flat tree), launch d (d = 1, 2,
+// 4, ..) one per pair of heads at distance d; flags carry the launch's epoch.
+struct QrChain {
+    int top, mfirst, end, epoch;
+    bool geqrt, tt;
+};
 
-// Producer workgroup b of one QR step: block b of GEQRT(A_kk), then block b
-// of each TSQRT(A_kk, A_ik) in order of i (units i0..i1-1 by the mode).
-// akk, tkk: where the GEQRT unit works instead of tile (k,k) and its T factor
-// (the A2 panel's FP64 copy).
+LQ_DEV QrChain qr_chain(const Ctx &c, int k, int d, int idx) {
+    const QrTree tr(c.n, k, c.qtree);
+    QrChain ch;
+    if (d == 0) {
+        ch.top = tr.head(idx); ch.mfirst = ch.top + 1; ch.end = tr.end(idx);
+        ch.geqrt = true; ch.tt = false; ch.epoch = qr_epoch(k, 0);
+    } else {
+        const int g0 = 2 * d * idx;
+        ch.top = tr.head(g0); ch.mfirst = tr.head(g0 + d); ch.end = ch.mfirst + 1;
+        ch.geqrt = false; ch.tt = true; ch.epoch = qr_epoch(k, QrTree::level(d));
+    }
+    return ch;
+}
+
+// Variant A2 (Sec. 2.3) factors A_kk in its panel, before the decision
+// (k_a2_geqrt, which publishes the flags of tile k); a QR step then continues
+// from it (QR_REST: the producers of the chain topped by tile k skip its GEQRT
+// unit, its consumers still apply the UNMQR blocks).
+enum QrMode { QR_FULL = 0, QR_REST = 1 };
+
+// Producer workgroup b of one chain: block b of GEQRT(top) (unless skipped),
+// then block b of each TSQRT/TTQRT(top, A_ik) in order of i.  Unit (i, b)
+// needs the trailing update of unit (i, b-1) (flag) and R's row block b (its
+// own previous unit).  akk, tkk: where the GEQRT unit works instead of the
+// top tile and its T factor (the A2 panel's FP64 copy).
 template <int NB, int P, bool PRE>
-LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem, int mode, typename Tr<P>::S *akk = nullptr,
-                        typename Tr<P>::S *tkk = nullptr) {
+LQ_DEV void qr_producer(const Ctx &c, int k, const QrChain &ch, int b, char *smem, bool skip_geqrt,
+                        typename Tr<P>::S *akk = nullptr, typename Tr<P>::S *tkk = nullptr) {
     typedef typename Tr<P>::S S;
     constexpr int PP = (P == PB16) ? P32 : P;  // panel-internal updates stay in the storage precision
     S *Ys = (S *)smem;
@@ -559,21 +596,20 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem, int mode, typena
     PanelLds *pl = (PanelLds *)(Rb + IB * IB);
     __shared__ int bail;
     S *At = (S *)c.At;
-    S *Tf = (S *)c.Tf;
+    S *Tq = (S *)(ch.tt ? c.Tt : c.Tf);
     const int tid = threadIdx.x;
-    const int epoch = k + 1;
+    const int epoch = ch.epoch;
     const int c0 = b * IB;
-    S *Akk = akk ? akk : At + c.toff(k, k);
-    const int i0 = mode == QR_REST ? k + 1 : k, i1 = mode == QR_GEQRT ? k + 1 : (int)c.n;
-    for (int i = i0; i < i1; ++i) {
+    S *Akk = akk ? akk : At + c.toff(ch.top, k);
+    for (int i = (ch.geqrt && !skip_geqrt) ? ch.top : ch.mfirst; i < ch.end; ++i) {
         if (b > 0) {  // the trailing update of unit (i, b-1) must be in place
             if (tid == 0) bail = !flag_wait(qr_flag(c, i, b - 1), epoch, &c.st->watchdog);
             __syncthreads();
             if (bail) return;
             fence_acquire();
         }
-        S *Ti = (i == k && tkk) ? tkk : Tf + c.tqoff(i, k);
-        if (i == k) {
+        S *Ti = (i == ch.top && tkk) ? tkk : Tq + c.tqoff(i, k);
+        if (i == ch.top) {
             panel_qr<NB, S, false>(Akk, c0, nullptr, Ys, Ts, pl);
             for (int e = tid; e < IB * IB; e += WG) Ti[(c0 + e % IB) + (c0 + e / IB) * NB] = Ts[e];
             panel_trailing<NB, PP, false, PRE>(Akk, nullptr, b, Ys, Ts);
@@ -584,13 +620,15 @@ LQ_DEV void qr_producer(const Ctx &c, int k, int b, char *smem, int mode, typena
                 Rb[e] = p <= q ? Akk[(c0 + p) + (c0 + q) * NB] : (S)0;
             }
             __syncthreads();
-            panel_qr<NB, S, true>(Aik, c0, Rb, Ys, Ts, pl);
+            if (ch.tt) panel_qr<NB, S, true, true>(Aik, c0, Rb, Ys, Ts, pl);
+            else panel_qr<NB, S, true>(Aik, c0, Rb, Ys, Ts, pl);
             for (int e = tid; e < IB * IB; e += WG) {
                 const int p = e % IB, q = e / IB;
                 if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[p * IB + q];
                 Ti[(c0 + p) + (c0 + q) * NB] = Ts[e];
             }
-            panel_trailing<NB, PP, true, PRE>(Aik, Akk, b, Ys, Ts);
+            if (ch.tt) panel_trailing<NB, PP, true, PRE, true>(Aik, Akk, b, Ys, Ts);
+            else panel_trailing<NB, PP, true, PRE>(Aik, Akk, b, Ys, Ts);
         }
         fence_release();  // every thread's writes of unit (i, b) before the flag
         __syncthreads();
@@ -612,8 +650,13 @@ template <int NB, int P> constexpr int qr_step_lds() {
 }
 template <int NB, int P> constexpr int qr_occ() { return qr_step_lds<NB, P>() <= 80 * 1024 ? 2 : 1; }
 
+// Launch d of QR step k (d = 0: the groups' chains; d > 0: the TT level at
+// distance d): the chains' producers first (nb/IB workgroups per chain, so
+// they are dispatched before any consumer and a consumer never waits on an
+// unscheduled producer), then per chain one consumer per 64-column strip of
+// every trailing tile column.
 template <int NB, int P>
-__global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k, int mode) {
+__global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k, int mode, int d) {
     if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
@@ -621,14 +664,22 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     constexpr int NBLK = NB / IB;
     constexpr bool PRE = false;  // bulk operand loads would exceed the registers at nb >= 256
     __shared__ __attribute__((aligned(16))) char smem[qr_step_lds<NB, P>()];
-    if ((int)blockIdx.x < qr_pw<NB>()) {
-        qr_producer<NB, P, PRE>(c, k, (int)blockIdx.x, smem, mode);
+    const QrTree tr(c.n, k, c.qtree);
+    const int nch = d == 0 ? tr.G : tr.npairs(d);
+    const int cps = ((int)c.n - k - 1) * qr_spc<NB>();  // consumers per chain
+    if ((int)blockIdx.x < nch * qr_pw<NB>()) {
+        const int idx = (int)blockIdx.x / qr_pw<NB>();
+        qr_producer<NB, P, PRE>(c, k, qr_chain(c, k, d, idx), (int)blockIdx.x % qr_pw<NB>(), smem,
+                                mode == QR_REST && d == 0 && idx == 0);
         return;
     }
+    if (cps == 0) return;
+    const int cidx = (int)blockIdx.x - nch * qr_pw<NB>();
+    const QrChain ch = qr_chain(c, k, d, cidx / cps);
     // Consumer: one 64-column strip of trailing tile column j.  The blocks it
-    // applies form one sequence s = 0 .. (n-k)*NBLK-1: block b of tile i =
-    // k + s/NBLK, first the UNMQR blocks of the GEQRT tile (i = k) on A_kj,
-    // then the TSMQR blocks of every A_ik on (A_kj, A_ij).  Block s+1 is
+    // applies form one sequence s = 0 .. nblocks-1: block b of tile i = t0 +
+    // s/NBLK, first (geqrt) the UNMQR blocks of the top tile on its own strip
+    // A_top,j, then the TSMQR (TTMQR) blocks of every A_ik on (A_top,j, A_ij).  Block s+1 is
     // loaded into registers before block s is applied and stored into the
     // other LDS buffer afterwards, so each block costs one barrier.
     // Cache invalidation is the expensive half of acquiring a block (several
@@ -639,10 +690,10 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     // Thread 0 keeps the index `covered` up to which blocks are acquired; the
     // flag that would extend it is read early and waited on only if unset.
     S *At = (S *)c.At;
-    S *Tf = (S *)c.Tf;
-    const int epoch = k + 1;
+    S *Tq = (S *)(ch.tt ? c.Tt : c.Tf);
+    const int epoch = ch.epoch;
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
-    const int strip = (int)blockIdx.x - qr_pw<NB>();
+    const int strip = cidx % cps;
     const int j = k + 1 + strip / qr_spc<NB>();
     const int col0 = (strip % qr_spc<NB>()) * 64 + 16 * w;
     const bool active = col0 < NB;
@@ -650,12 +701,13 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     S *const Y0 = (S *)smem;          // staging buffer u: V at Y0 + u*VB, T at T0 + u*IB*IB
     S *const T0 = Y0 + 2 * VB;
     __shared__ int bail[2], inval[2];  // for block x: slot x & 1
-    S *Akj = At + c.toff(k, j);
-    S *const topc = Akj + (col0 + i16) * NB;  // this lane's column of A_kj for the TSMQR blocks
-    const int nblocks = (c.n - k) * NBLK;
-    auto vtile = [&](int s) { return At + c.toff(k + s / NBLK, k); };
-    auto ttile = [&](int s) { return Tf + c.tqoff(k + s / NBLK, k); };
-    auto flag_of = [&](int s) { return qr_flag(c, k + s / NBLK, s % NBLK); };
+    S *Akj = At + c.toff(ch.top, j);
+    S *const topc = Akj + (col0 + i16) * NB;  // this lane's column of A_top,j for the TSMQR blocks
+    const int t0 = ch.geqrt ? ch.top : ch.mfirst;
+    const int nblocks = (ch.end - t0) * NBLK;
+    auto vtile = [&](int s) { return At + c.toff(t0 + s / NBLK, k); };
+    auto ttile = [&](int s) { return Tq + c.tqoff(t0 + s / NBLK, k); };
+    auto flag_of = [&](int s) { return qr_flag(c, t0 + s / NBLK, s % NBLK); };
     acc_t bot[NB / 16];
     auto load_bot = [&](const S *src) {
 #pragma unroll
@@ -682,14 +734,15 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     __syncthreads();
     if (bail[0] || bail[1]) return;
     fence_acquire();
-    if (active) load_bot(Akj);
-    stage_block<NB, S, true>(vtile(0), ttile(0), 0, Y0, T0);
+    if (active) load_bot(At + c.toff(t0, j));
+    if (ch.geqrt) stage_block<NB, S, 1>(vtile(0), ttile(0), 0, Y0, T0);
+    else stage_block<NB, S, 2>(vtile(0), ttile(0), 0, Y0, T0);  // a TT chain
     __syncthreads();
     for (int s = 0; s < nblocks; ++s) {
         const int cur = s & 1;
         const bool has_next = s + 1 < nblocks;
         if (has_next && bail[(s + 1) & 1]) return;  // the flag of block s+1 was never set
-        const int i = k + s / NBLK, b = s % NBLK;
+        const int i = t0 + s / NBLK, b = s % NBLK;
         StageRegs<NB, S> nx;
         if (has_next) {
             if (inval[(s + 1) & 1]) cache_invalidate();
@@ -702,17 +755,18 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
                                          __HIP_MEMORY_SCOPE_AGENT);
         if (active) {
             const S *Yc = Y0 + cur * VB, *Tc = T0 + cur * (IB * IB);
-            if (i == k) apply_block<NB, P, false, PRE>(bot, nullptr, b, Yc, Tc);
+            if (i == ch.top) apply_block<NB, P, false, PRE>(bot, nullptr, b, Yc, Tc);
             else apply_block<NB, P, true, PRE>(bot, topc, b, Yc, Tc);
             if (b == NBLK - 1) {  // tile i done: write it back, start on the next
-                store_bot(i == k ? Akj : At + c.toff(i, j));
-                if (i + 1 < c.n) load_bot(At + c.toff(i + 1, j));
+                store_bot(i == ch.top ? Akj : At + c.toff(i, j));
+                if (i + 1 < ch.end) load_bot(At + c.toff(i + 1, j));
             }
         }
         if (has_next) {
             S *Yn = Y0 + (cur ^ 1) * VB, *Tn = T0 + (cur ^ 1) * (IB * IB);
-            if ((s + 1) / NBLK == 0) stage_store<NB, S, true>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
-            else stage_store<NB, S, false>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
+            if (t0 + (s + 1) / NBLK == ch.top) stage_store<NB, S, 1>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
+            else if (ch.tt) stage_store<NB, S, 2>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
+            else stage_store<NB, S, 0>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
         }
         if (tid == 0 && s + 2 < nblocks) {
             int bl = 0, inv = 0;
@@ -739,7 +793,10 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
 template <int NB>
 __global__ __launch_bounds__(WG) void k_a2_geqrt(Ctx c, int k) {
     __shared__ __attribute__((aligned(16))) char smem[qr_lds<NB, P64>()];
-    qr_producer<NB, P64, false>(c, k, (int)blockIdx.x, smem, QR_GEQRT, c.W + (size_t)k * NB * NB,
+    QrChain ch;  // the GEQRT unit of tile k alone
+    ch.top = k; ch.mfirst = k + 1; ch.end = k + 1; ch.epoch = qr_epoch(k, 0);
+    ch.geqrt = true; ch.tt = false;
+    qr_producer<NB, P64, false>(c, k, ch, (int)blockIdx.x, smem, false, c.W + (size_t)k * NB * NB,
                                 c.Dinv + (size_t)k * NB * NB);
 }
 
@@ -766,8 +823,11 @@ template <int NB> constexpr int qr_npairs() {
 
 // Gram blocks G(a, b) = V_a^T V_b in FP64 (MFMA), one GB x GB block per
 // workgroup; grid (pairs, n-k).
+// tt = 0: every panel tile's own reflectors (GEQRT for the heads of the
+// elimination tree, tile k alone in the flat tree; TS for the rest); tt = 1:
+// the TT reflectors of the killed heads (upper triangular tails).
 template <int NB, int P>
-__global__ __launch_bounds__(WG) void k_qr_gram(Ctx c, int k) {
+__global__ __launch_bounds__(WG) void k_qr_gram(Ctx c, int k, int tt) {
     if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
     __shared__ __attribute__((aligned(16))) char smem[mma_lds_bytes<P64, GB, GB, 16>()];
@@ -775,10 +835,12 @@ __global__ __launch_bounds__(WG) void k_qr_gram(Ctx c, int k) {
     while (p >= bb + (IB < GB)) { p -= bb + (IB < GB); ++bb; }
     const int a0 = p * GB, b0 = bb * GB;
     const int t = blockIdx.y, i = k + t;
+    const bool head = QrTree(c.n, k, c.qtree).is_head(i);
+    if (tt && (!head || i == k)) return;
     const S *V = (const S *)c.At + c.toff(i, k);
-    const bool ts = i > k;
     auto v = [&](int r, int col) -> double {
-        if (ts) return (double)V[r + (size_t)col * NB];
+        if (tt) return r <= col ? (double)V[r + (size_t)col * NB] : 0.0;
+        if (!head) return (double)V[r + (size_t)col * NB];
         return r < col ? 0.0 : (r == col ? 1.0 : (double)V[r + (size_t)col * NB]);
     };
     Tr<P64>::acc acc[1][1];
@@ -797,8 +859,12 @@ __global__ __launch_bounds__(WG) void k_qr_gram(Ctx c, int k) {
 // workspace does not hold, is masked to zero on staging); thread (a1, q)
 // accumulates rows a1 + AS m of column q.
 template <int NB, int P>
-__global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k) {
+__global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k, int tt) {
     if (c.dec[k] != 0) return;
+    if (tt) {  // the TT pass: the killed heads only
+        const int i = k + (int)blockIdx.x;
+        if (i == k || !QrTree(c.n, k, c.qtree).is_head(i)) return;
+    }
     typedef typename Tr<P>::S S;
     constexpr int AS = WG / IB;         // row stride: thread tid takes rows tid/IB + AS m
     constexpr int MR = (NB - IB) / AS;  // rows a per thread at most
@@ -808,7 +874,7 @@ __global__ __launch_bounds__(WG) void k_qr_tfull(Ctx c, int k) {
     __shared__ double Y1[(NB - IB) * IB];  // Y1[a*IB + p]
     __shared__ double Tb[IB * IB];
     const int t = blockIdx.x, i = k + t;
-    S *T = (S *)c.Tf + c.tqoff(i, k);
+    S *T = (S *)(tt ? c.Tt : c.Tf) + c.tqoff(i, k);
     const double *G = c.gram + (size_t)t * NB * NB;
     const int tid = threadIdx.x, q = tid & (IB - 1), a1 = tid / IB;
     for (int b = 1; b < NB / IB; ++b) {

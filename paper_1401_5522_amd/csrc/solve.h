@@ -217,6 +217,7 @@ static __global__ __launch_bounds__(WG) void k_fwd_qr_g(Ctx c, SolveArgs s, int 
     constexpr int RQ = rq<NB>(), QS = qs<NB>();
     __shared__ double ys[NB * RQ];
     const int i = k + 1 + (int)blockIdx.x / QS;
+    if (QrTree(c.n, k, c.qtree).is_head(i)) return;  // a head's row: its GEQRT in the chain, TT below
     const int part = (int)blockIdx.x % QS;
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
     const int64_t Np = c.n * NB;
@@ -226,13 +227,16 @@ static __global__ __launch_bounds__(WG) void k_fwd_qr_g(Ctx c, SolveArgs s, int 
                                 part * (NB / QS), (part + 1) * (NB / QS));
 }
 
-// QR step, part 2 (one workgroup per rhs chunk): the flat tree applied to the
-// eliminator row.  First z = Q_kk^T y_k = z - V T^T V^T z (GEQRT tile), then
-// for i = k+1.. in order, with the full TS factor of tile (i,k),
+// QR step, part 2 (one workgroup per group of the elimination tree and rhs
+// chunk; the flat tree is one group headed by tile k): the group's chain
+// applied to its head row h.  First z = Q_hh^T y_h = z - V T^T V^T z (GEQRT
+// tile), then for the group's tiles i = h+1.. in order, with the full TS
+// factor of tile (i,k),
 //   w_i = T_ik^T (z + g_i),  z -= w_i,
 // which is the top half of [z; y_i] <- Q_ik^T [z; y_i] (V = [I; Y_ik]); the
 // bottom half y_i -= Y_ik w_i is independent of the chain and left to part 3.
-// Only the triangular T factors are read inside the chain.
+// Only the triangular T factors are read inside the chain.  z goes to Z_k
+// (flat tree) or back to y_h for the TT levels (k_fwd_tt).
 // threads of the chain workgroup: eight waves for 4-byte storage (T read into
 // registers for n_b <= 256), sixteen for 8-byte storage (T read from memory:
 // its registers would not fit beside the rest)
@@ -354,13 +358,15 @@ static __global__ __launch_bounds__((chain_wg<NB, S>())) void k_fwd_qr_chain(Ctx
     const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
     const int64_t Np = c.n * NB;
     const S *At = (const S *)c.At, *Tf = (const S *)c.Tf;
-    const S *V = At + c.toff(k, k);
+    const QrTree tr(c.n, k, c.qtree);
+    const int h = tr.head((int)blockIdx.x), iend = tr.end((int)blockIdx.x);
+    const S *V = At + c.toff(h, k);
     auto gidx = [&](int i, int e) { return (int64_t)i * NB + e % NB + (int64_t)(q0 + e / NB) * Np; };
-    for (int e = tid; e < NB * nq; e += CHAIN_WG) x[e] = s.Y[gidx(k, e)];
+    for (int e = tid; e < NB * nq; e += CHAIN_WG) x[e] = s.Y[gidx(h, e)];
     __syncthreads();
     cols_dot<NB, NW, 2, S>(V, x, nq, u, NB, 0, NB);  // u = V^T z
     __syncthreads();
-    cols_dot<NB, NW, 1, S>(Tf + c.tqoff(k, k), u, nq, w, NB, 0, NB);  // w = T^T u
+    cols_dot<NB, NW, 1, S>(Tf + c.tqoff(h, k), u, nq, w, NB, 0, NB);  // w = T^T u
     __syncthreads();
     for (int e = tid; e < NB * nq; e += CHAIN_WG) {  // z -= V w (V unit lower triangular)
         const int r = e % NB, q = e / NB;
@@ -379,18 +385,18 @@ static __global__ __launch_bounds__((chain_wg<NB, S>())) void k_fwd_qr_chain(Ctx
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         const int e = tid + p * CHAIN_WG;
-        gn[p] = (k + 1 < c.n && e < NB * nq) ? s.G[gidx(k + 1, e)] : 0.0;
+        gn[p] = (h + 1 < iend && e < NB * nq) ? s.G[gidx(h + 1, e)] : 0.0;
     }
     // T of the next two tiles in registers (4-byte storage, n_b <= 256)
     constexpr bool REG = NB <= 256 && sizeof(S) == 4;
     constexpr int PD = REG ? 2 : 1;
     ChainR<(REG ? NB : 32), float> ta, tb;
     if constexpr (REG) {
-        if (k + 1 < c.n) ta.load((const float *)Tf + c.tqoff(k + 1, k));
+        if (h + 1 < iend) ta.load((const float *)Tf + c.tqoff(h + 1, k));
         if constexpr (PD == 2)
-            if (k + 2 < c.n) tb.load((const float *)Tf + c.tqoff(k + 2, k));
+            if (h + 2 < iend) tb.load((const float *)Tf + c.tqoff(h + 2, k));
     }
-    auto step = [&](int i, ChainR<(REG ? NB : 32), float> &tr) __attribute__((always_inline)) {
+    auto step = [&](int i, ChainR<(REG ? NB : 32), float> &tc) __attribute__((always_inline)) {
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int e = tid + p * CHAIN_WG;
@@ -400,11 +406,11 @@ static __global__ __launch_bounds__((chain_wg<NB, S>())) void k_fwd_qr_chain(Ctx
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int e = tid + p * CHAIN_WG;
-            gn[p] = (i + 1 < c.n && e < NB * nq) ? s.G[gidx(i + 1, e)] : 0.0;
+            gn[p] = (i + 1 < iend && e < NB * nq) ? s.G[gidx(i + 1, e)] : 0.0;
         }
         if constexpr (REG) {
-            tr.apply(u, nq, w);
-            if (i + PD < c.n) tr.load((const float *)Tf + c.tqoff(i + PD, k));
+            tc.apply(u, nq, w);
+            if (i + PD < iend) tc.load((const float *)Tf + c.tqoff(i + PD, k));
         } else {
             cols_dot<NB, NW, 1, S>(Tf + c.tqoff(i, k), u, nq, w, NB, 0, NB);
         }
@@ -418,18 +424,68 @@ static __global__ __launch_bounds__((chain_wg<NB, S>())) void k_fwd_qr_chain(Ctx
             }
         }
     };
-    for (int i = k + 1; i < c.n; i += PD) {
+    for (int i = h + 1; i < iend; i += PD) {
         step(i, ta);
         if constexpr (PD == 2)
-            if (i + 1 < c.n) step(i + 1, tb);
+            if (i + 1 < iend) step(i + 1, tb);
     }
-    for (int e = tid; e < NB * nq; e += CHAIN_WG) s.Z[gidx(k, e)] = x[e];
+    double *out = c.qtree ? s.Y : s.Z;  // a tree: the heads' rows go on to the TT levels
+    for (int e = tid; e < NB * nq; e += CHAIN_WG) out[gidx(h, e)] = x[e];
+}
+
+// QR step with an elimination tree, the TT level at distance d (grid: pairs,
+// rhs chunks): [y_h0; y_h1] <- Q^T [y_h0; y_h1] for the TT reflectors V =
+// [I; Y] of the killed head h1 (Y upper triangular in tile (h1,k), T in Tt):
+// w = T^T (y_h0 + Y^T y_h1), y_h0 -= w, y_h1 -= Y w.
+template <int NB, class S>
+static __global__ __launch_bounds__(WG) void k_fwd_tt(Ctx c, SolveArgs s, int k, int d) {
+    if (c.dec[k] != 0 || gated(s.gate)) return;
+    constexpr int RQ = rq<NB>(), NW = WG / 64;
+    __shared__ double y0[NB * RQ], y1[NB * RQ], u[NB * RQ], w[NB * RQ];
+    __shared__ double red[4 * RQ * 64];
+    const QrTree tr(c.n, k, c.qtree);
+    const int g0 = 2 * d * (int)blockIdx.x;
+    const int h0 = tr.head(g0), h1 = tr.head(g0 + d);
+    const int q0 = blockIdx.y * RQ, nq = min(RQ, s.nrhs - q0);
+    const int64_t Np = c.n * NB;
+    auto gidx = [&](int i, int e) { return (int64_t)i * NB + e % NB + (int64_t)(q0 + e / NB) * Np; };
+    const S *Y = (const S *)c.At + c.toff(h1, k);
+    const S *T = (const S *)c.Tt + c.tqoff(h1, k);
+    for (int e = threadIdx.x; e < NB * nq; e += WG) {
+        y0[e] = s.Y[gidx(h0, e)];
+        y1[e] = s.Y[gidx(h1, e)];
+    }
+    __syncthreads();
+    cols_dot<NB, NW, 1, S>(Y, y1, nq, u, NB, 0, NB);  // u = Y^T y1 (upper triangle of the tile)
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * nq; e += WG) u[e] += y0[e];
+    __syncthreads();
+    cols_dot<NB, NW, 1, S>(T, u, nq, w, NB, 0, NB);  // w = T^T u
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * nq; e += WG) s.Y[gidx(h0, e)] = y0[e] - w[e];
+    for (int r0 = 0; r0 < NB; r0 += mv_rb<NB>()) {  // y1 -= Y w
+        double out[RQ];
+        if (rows_mv<NB, 1>(Y, w, nq, r0, out, red))
+            for (int q = 0; q < nq; ++q) s.Y[gidx(h1, r0 + lane_id() + q * NB)] = y1[q * NB + r0 + lane_id()] - out[q];
+        __syncthreads();
+    }
+}
+
+// After the TT levels: z_k = y_k (the eliminator row's transformed right-hand
+// sides, for the back substitution).
+template <int NB>
+static __global__ __launch_bounds__(WG) void k_fwd_tt_fin(Ctx c, SolveArgs s, int k) {
+    if (c.dec[k] != 0 || gated(s.gate)) return;
+    const int64_t Np = c.n * NB;
+    for (int64_t e = blockIdx.x * (int64_t)WG + threadIdx.x; e < (int64_t)NB * s.nrhs; e += (int64_t)gridDim.x * WG)
+        s.Z[(int64_t)k * NB + e % NB + (e / NB) * Np] = s.Y[(int64_t)k * NB + e % NB + (e / NB) * Np];
 }
 
 // QR step, part 3: y_i -= Y_ik w_i for i > k.
 template <int NB, class S>
 static __global__ __launch_bounds__(WG) void k_fwd_qr_u(Ctx c, SolveArgs s, int k) {
     if (c.dec[k] != 0 || gated(s.gate)) return;
+    if (QrTree(c.n, k, c.qtree).is_head(k + 1 + (int)blockIdx.x / (NB / mv_rb<NB>()))) return;
     tile_update<NB, S, 1>(c, s, k, k + 1, s.Y);
 }
 

@@ -35,7 +35,7 @@ class Factors:
 
     def __init__(self, A, nb, criterion="max", alpha=1.0, precision="fp64", nrhs_max=1, seed=0,
                  forced=None, nsteps=-1, timing=False, work=None, lookahead=True, domain=0, estimate=False,
-                 variant=1):
+                 variant=1, tree=0):
         A = colmajor(A)
         self.N = N = A.shape[0]
         self._lda = N
@@ -43,7 +43,7 @@ class Factors:
         self.n = (N + nb - 1) // nb
         self.precision = precision
         self.opts, self._keep = L.make_opts(nb, criterion, alpha, precision, nrhs_max, seed, forced, nsteps,
-                                            timing, lookahead, domain, estimate, variant)
+                                            timing, lookahead, domain, estimate, variant, tree)
         nbytes = L.luqr_workspace_bytes(N, self.opts)
         if work is None or work.numel() < nbytes + 256:
             work = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")

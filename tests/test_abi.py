@@ -29,9 +29,10 @@ def test_library_exports_every_symbol():
 
 def test_struct_layouts_match_header():
     from paper_1401_5522_amd import _lib
-    assert C.sizeof(_lib.luqr_opts) == 64
+    assert C.sizeof(_lib.luqr_opts) == 72
     assert _lib.luqr_opts.invnorm_estimate.offset == 56
     assert _lib.luqr_opts.lu_variant.offset == 60
+    assert _lib.luqr_opts.qr_tree.offset == 64
     assert _lib.luqr_opts.forced.offset == 32
     assert C.sizeof(_lib.luqr_status) == 40
     assert _lib.luqr_status.ir_eta.offset == 24
@@ -94,6 +95,27 @@ def test_lu_variant_validation_without_gpu():
         o, _ = _lib.make_opts(64, variant=2, **kw)
         assert L.luqr_workspace_bytes(256, C.byref(o)) == _lib.LUQR_ERR_UNSUPPORTED, kw
     o, _ = _lib.make_opts(64, precision="fp32", variant=2)  # batched: FP32 and A1 only, checked before any GPU call
+    plan = C.c_void_p()
+    Ns = np.array([64], np.int64)
+    ld = np.array([64], np.int64)
+    rc = L.luqr_batched_plan(1, Ns.ctypes.data, None, ld.ctypes.data, ld.ctypes.data, ld.ctypes.data, C.byref(o),
+                             4, C.c_void_p(256), 1 << 30, C.byref(plan))
+    assert rc == _lib.LUQR_ERR_UNSUPPORTED
+
+
+def test_qr_tree_validation_without_gpu():
+    from paper_1401_5522_amd import _lib
+    L = _lib.lib()
+    o0, _ = _lib.make_opts(64)
+    o1, _ = _lib.make_opts(64, tree=2)
+    b0 = L.luqr_workspace_bytes(1024, C.byref(o0))
+    b1 = L.luqr_workspace_bytes(1024, C.byref(o1))
+    n = 1024 // 64
+    # one more T factor per panel tile (in place of a 256-byte placeholder)
+    assert b1 - b0 == n * (n + 1) // 2 * 64 * 64 * 8 - 256
+    o, _ = _lib.make_opts(64, tree=-1)
+    assert L.luqr_workspace_bytes(1024, C.byref(o)) == -2
+    o, _ = _lib.make_opts(64, precision="fp32", tree=2)
     plan = C.c_void_p()
     Ns = np.array([64], np.int64)
     ld = np.array([64], np.int64)
