@@ -73,6 +73,9 @@ def parse():
                          "profiled runs skip the factorizations that build U and V)")
     ap.add_argument("--estimate", action="store_true",
                     help="take ||A_kk^-1||_1 from the O(n_b^2) iterative estimate (Sec. 3.4) instead of exactly")
+    ap.add_argument("--qr-tree", type=int, default=0, metavar="S",
+                    help="QR steps' elimination tree: 0 = flat TS (Alg. 4a); S > 0 = TS within groups of S panel "
+                         "tiles and a binary TT tree over their heads (Alg. 3/4, Sec. 2.2)")
     ap.add_argument("--lu-variant", type=int, default=1, choices=(1, 2),
                     help="LU step: 1 = A1 (GEPP on a backup of A_kk, Alg. 2); 2 = A2 (GEQRT of A_kk first, "
                          "kept by a QR step; Sec. 2.3)")
@@ -182,6 +185,8 @@ def roofline(n, nb, prec, dec, times, N):
         launches = n - 1                             # launched while trailing tiles remain
         flops = lu_update_flops(n, nb, dec)
         avg_ms = float(col[:, : n - 1].mean())
+    # with an elimination tree the QR phase of a step is 1 + log2(groups)
+    # launches of the kernel; the figures are then per step
     per_launch = flops / launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
@@ -211,7 +216,7 @@ def cpu_baseline(args, solver, torch):
     b = inputs.rhs(Ns, 1, seed=(args.seed,))
     t0 = time.perf_counter()
     fo = O.factor(A, args.nb, args.criterion, args.alpha, seed=args.seed, estimate=args.estimate,
-                  variant=args.lu_variant)
+                  variant=args.lu_variant, tree=args.qr_tree)
     xo = fo.solve(b)
     t = time.perf_counter() - t0
     eta_o = O.backward_error(A, xo, b)
@@ -219,7 +224,7 @@ def cpu_baseline(args, solver, torch):
     Ad = torch.from_numpy(A).cuda()
     bd = torch.from_numpy(b).cuda()
     f = solver.factor(Ad, args.nb, criterion=args.criterion, alpha=args.alpha, seed=args.seed,
-                      precision=args.precision, estimate=args.estimate, variant=args.lu_variant)
+                      precision=args.precision, estimate=args.estimate, variant=args.lu_variant, tree=args.qr_tree)
     x = f.solve_refined(Ad, bd, max_iter=args.max_iter) if args.precision != "fp64" else f.solve(bd)
     dec, _, _, mg = f.decisions()
     band = DECISION_BAND[args.precision]
@@ -231,7 +236,8 @@ def cpu_baseline(args, solver, torch):
         "cores": O.num_threads(),
         "kind": "oracle",
         "sample": f"FP64 oracle factor+solve, usv kappa={args.kappa:g} N={Ns} nb={args.nb} "
-                  f"{args.criterion} alpha={args.alpha:g}{' A2' if args.lu_variant == 2 else ''}, 1 RHS ({t:.1f} s)",
+                  f"{args.criterion} alpha={args.alpha:g}{' A2' if args.lu_variant == 2 else ''}"
+                  f"{f' tree={args.qr_tree}' if args.qr_tree else ''}, 1 RHS ({t:.1f} s)",
         "seconds": round(t, 3),
         "eta_oracle": eta_o,
         "eta_gpu": eta_g,
@@ -444,7 +450,7 @@ def main():
     B = B.t().contiguous().t()
     torch.cuda.synchronize()
     kw = dict(criterion=args.criterion, alpha=args.alpha, seed=args.seed, nrhs_max=args.nrhs, estimate=args.estimate,
-              variant=args.lu_variant)
+              variant=args.lu_variant, tree=args.qr_tree)
 
     nb64 = min(nb, 256)  # the FP64 path stops at n_b = 256
 
@@ -542,7 +548,8 @@ def main():
                    "refine": args.refine,
                    "alpha": args.alpha, "precision": prec, "parallelism": "single GPU",
                    "inverse_norm": "estimate" if args.estimate else "exact",
-                   "lu_variant": "A2" if args.lu_variant == 2 else "A1"},
+                   "lu_variant": "A2" if args.lu_variant == 2 else "A1",
+                   "qr_tree": f"TS groups of {args.qr_tree}, binary TT" if args.qr_tree else "flat TS"},
         "solves_per_s": round(1e3 / ms, 4),
         "eta": eta,
         "eta_target": N * 1e-16,

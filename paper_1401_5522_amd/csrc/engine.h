@@ -96,8 +96,9 @@ struct Eng {
                 const QrTree tr(n, k, c.qtree);
                 const int mode = c.a2 ? QR_REST : QR_FULL;
                 const unsigned per = qr_pw<NB>() + rest * qr_spc<NB>();
-                k_qr_step<NB, P><<<tr.G * per, WG, 0, st>>>(c, k, mode, 0);
-                for (int d = 1; d < tr.G; d *= 2) k_qr_step<NB, P><<<tr.npairs(d) * per, WG, 0, st>>>(c, k, mode, d);
+                k_qr_step<NB, P, false><<<tr.G * per, WG, 0, st>>>(c, k, mode, 0);
+                for (int d = 1; d < tr.G; d *= 2)
+                    k_qr_step<NB, P, true><<<tr.npairs(d) * per, WG, 0, st>>>(c, k, mode, d);
             }
             if (ev) (void)hipEventRecord(ev[E * k + 4], st);
             hipStream_t sb = st;

@@ -585,7 +585,7 @@ enum QrMode { QR_FULL = 0, QR_REST = 1 };
 // needs the trailing update of unit (i, b-1) (flag) and R's row block b (its
 // own previous unit).  akk, tkk: where the GEQRT unit works instead of the
 // top tile and its T factor (the A2 panel's FP64 copy).
-template <int NB, int P, bool PRE>
+template <int NB, int P, bool PRE, bool TT>
 LQ_DEV void qr_producer(const Ctx &c, int k, const QrChain &ch, int b, char *smem, bool skip_geqrt,
                         typename Tr<P>::S *akk = nullptr, typename Tr<P>::S *tkk = nullptr) {
     typedef typename Tr<P>::S S;
@@ -596,7 +596,7 @@ LQ_DEV void qr_producer(const Ctx &c, int k, const QrChain &ch, int b, char *sme
     PanelLds *pl = (PanelLds *)(Rb + IB * IB);
     __shared__ int bail;
     S *At = (S *)c.At;
-    S *Tq = (S *)(ch.tt ? c.Tt : c.Tf);
+    S *Tq = (S *)(TT ? c.Tt : c.Tf);
     const int tid = threadIdx.x;
     const int epoch = ch.epoch;
     const int c0 = b * IB;
@@ -620,15 +620,13 @@ LQ_DEV void qr_producer(const Ctx &c, int k, const QrChain &ch, int b, char *sme
                 Rb[e] = p <= q ? Akk[(c0 + p) + (c0 + q) * NB] : (S)0;
             }
             __syncthreads();
-            if (ch.tt) panel_qr<NB, S, true, true>(Aik, c0, Rb, Ys, Ts, pl);
-            else panel_qr<NB, S, true>(Aik, c0, Rb, Ys, Ts, pl);
+            panel_qr<NB, S, true, TT>(Aik, c0, Rb, Ys, Ts, pl);
             for (int e = tid; e < IB * IB; e += WG) {
                 const int p = e % IB, q = e / IB;
                 if (p <= q) Akk[(c0 + p) + (c0 + q) * NB] = Rb[p * IB + q];
                 Ti[(c0 + p) + (c0 + q) * NB] = Ts[e];
             }
-            if (ch.tt) panel_trailing<NB, PP, true, PRE, true>(Aik, Akk, b, Ys, Ts);
-            else panel_trailing<NB, PP, true, PRE>(Aik, Akk, b, Ys, Ts);
+            panel_trailing<NB, PP, true, PRE, TT>(Aik, Akk, b, Ys, Ts);
         }
         fence_release();  // every thread's writes of unit (i, b) before the flag
         __syncthreads();
@@ -650,12 +648,12 @@ template <int NB, int P> constexpr int qr_step_lds() {
 }
 template <int NB, int P> constexpr int qr_occ() { return qr_step_lds<NB, P>() <= 80 * 1024 ? 2 : 1; }
 
-// Launch d of QR step k (d = 0: the groups' chains; d > 0: the TT level at
-// distance d): the chains' producers first (nb/IB workgroups per chain, so
-// they are dispatched before any consumer and a consumer never waits on an
-// unscheduled producer), then per chain one consumer per 64-column strip of
-// every trailing tile column.
-template <int NB, int P>
+// Launch d of QR step k (d = 0: the groups' chains, TT = false; d > 0: the TT
+// level at distance d, TT = true): the chains' producers first (nb/IB
+// workgroups per chain, so they are dispatched before any consumer and a
+// consumer never waits on an unscheduled producer), then per chain one
+// consumer per 64-column strip of every trailing tile column.
+template <int NB, int P, bool TT>
 __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k, int mode, int d) {
     if (c.dec[k] != 0) return;
     typedef typename Tr<P>::S S;
@@ -669,8 +667,8 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     const int cps = ((int)c.n - k - 1) * qr_spc<NB>();  // consumers per chain
     if ((int)blockIdx.x < nch * qr_pw<NB>()) {
         const int idx = (int)blockIdx.x / qr_pw<NB>();
-        qr_producer<NB, P, PRE>(c, k, qr_chain(c, k, d, idx), (int)blockIdx.x % qr_pw<NB>(), smem,
-                                mode == QR_REST && d == 0 && idx == 0);
+        qr_producer<NB, P, PRE, TT>(c, k, qr_chain(c, k, d, idx), (int)blockIdx.x % qr_pw<NB>(), smem,
+                                    mode == QR_REST && d == 0 && idx == 0);
         return;
     }
     if (cps == 0) return;
@@ -690,7 +688,7 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     // Thread 0 keeps the index `covered` up to which blocks are acquired; the
     // flag that would extend it is read early and waited on only if unset.
     S *At = (S *)c.At;
-    S *Tq = (S *)(ch.tt ? c.Tt : c.Tf);
+    S *Tq = (S *)(TT ? c.Tt : c.Tf);
     const int epoch = ch.epoch;
     const int tid = threadIdx.x, l = lane_id(), w = wave_id();
     const int strip = cidx % cps;
@@ -735,8 +733,7 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     if (bail[0] || bail[1]) return;
     fence_acquire();
     if (active) load_bot(At + c.toff(t0, j));
-    if (ch.geqrt) stage_block<NB, S, 1>(vtile(0), ttile(0), 0, Y0, T0);
-    else stage_block<NB, S, 2>(vtile(0), ttile(0), 0, Y0, T0);  // a TT chain
+    stage_block<NB, S, TT ? 2 : 1>(vtile(0), ttile(0), 0, Y0, T0);  // a TT chain has no GEQRT tile
     __syncthreads();
     for (int s = 0; s < nblocks; ++s) {
         const int cur = s & 1;
@@ -755,7 +752,7 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
                                          __HIP_MEMORY_SCOPE_AGENT);
         if (active) {
             const S *Yc = Y0 + cur * VB, *Tc = T0 + cur * (IB * IB);
-            if (i == ch.top) apply_block<NB, P, false, PRE>(bot, nullptr, b, Yc, Tc);
+            if (!TT && i == ch.top) apply_block<NB, P, false, PRE>(bot, nullptr, b, Yc, Tc);
             else apply_block<NB, P, true, PRE>(bot, topc, b, Yc, Tc);
             if (b == NBLK - 1) {  // tile i done: write it back, start on the next
                 store_bot(i == ch.top ? Akj : At + c.toff(i, j));
@@ -764,8 +761,8 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
         }
         if (has_next) {
             S *Yn = Y0 + (cur ^ 1) * VB, *Tn = T0 + (cur ^ 1) * (IB * IB);
-            if (t0 + (s + 1) / NBLK == ch.top) stage_store<NB, S, 1>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
-            else if (ch.tt) stage_store<NB, S, 2>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
+            if constexpr (TT) stage_store<NB, S, 2>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
+            else if ((s + 1) / NBLK == 0) stage_store<NB, S, 1>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
             else stage_store<NB, S, 0>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
         }
         if (tid == 0 && s + 2 < nblocks) {
@@ -796,8 +793,8 @@ __global__ __launch_bounds__(WG) void k_a2_geqrt(Ctx c, int k) {
     QrChain ch;  // the GEQRT unit of tile k alone
     ch.top = k; ch.mfirst = k + 1; ch.end = k + 1; ch.epoch = qr_epoch(k, 0);
     ch.geqrt = true; ch.tt = false;
-    qr_producer<NB, P64, false>(c, k, ch, (int)blockIdx.x, smem, false, c.W + (size_t)k * NB * NB,
-                                c.Dinv + (size_t)k * NB * NB);
+    qr_producer<NB, P64, false, false>(c, k, ch, (int)blockIdx.x, smem, false, c.W + (size_t)k * NB * NB,
+                                       c.Dinv + (size_t)k * NB * NB);
 }
 
 // ---------------------------------------------------------------------------
