@@ -17,7 +17,9 @@
  *    (hipMalloc or torch CUDA tensors); "host pointer" means ordinary memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Every call only enqueues work on it and returns without waiting, except
- *    the luqr_get_* calls, which wait for the stream.
+ *    the luqr_get_* calls, which wait for the stream, luqr_solve_gmres_ir
+ *    (its Arnoldi least-squares runs on the host) and luqr_solve_noalloc with
+ *    a status to fill.
  *  - The library never allocates device memory: the caller provides one
  *    workspace whose size luqr_workspace_bytes reports and keeps it alive
  *    until luqr_destroy.  The library owns only the small host handle and,
@@ -160,21 +162,21 @@ int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_opts *opts,
  * using the stored factors: forward replay of the step transformations
  * (Sec. 2.4, second pass) then block back-substitution.  The arithmetic is
  * FP64 over factors in their storage precision; B and the result are FP64.
- * nrhs <= opts.nrhs_max.  The first solve on a handle waits once for the
- * factorization to finish and reads its decision sequence, so that every
- * solve launches only the kernels of the branch each step took; after that
- * the call only enqueues. */
+ * nrhs <= opts.nrhs_max.  Only enqueues: the kernels read each step's
+ * decision on the device (the kernels of the branch a step did not take
+ * return at once), so the host never waits for the factorization. */
 int luqr_solve(luqr_factors f, int64_t nrhs, double *dB, int64_t ldb, void *stream);
 
 /* Mixed-precision solve with FP64 iterative refinement: x0 = solve(b), then
  * up to max_iter times r = b - A x (FP64, from dA), d = solve(r) with the
  * stored factors, x += d (FP64), stopping once every column has
  * ||r||_inf <= N * 1e-16 * ||A||_inf ||x||_inf.  dA is the FP64 matrix that
- * was factored; dB is read, dX (N x nrhs, ldx) written.  The convergence test
- * runs on the device; the host reads its flag after each residual (a wait on
- * `stream`) to stop enqueuing, so this call returns when at most the final
- * copy to dX is still in flight.  Iteration count and final backward error
- * are reported by luqr_get_status. */
+ * was factored; dB is read, dX (N x nrhs, ldx) written.  Only enqueues: all
+ * max_iter passes are enqueued, the convergence test runs on the device, and
+ * once it has passed the kernels of the remaining passes return at once
+ * (each reads the device flag), so a pass after convergence costs only its
+ * launches.  Iteration count and final backward error are reported by
+ * luqr_get_status. */
 int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda, int64_t nrhs,
                        const double *dB, int64_t ldb, double *dX, int64_t ldx,
                        int32_t max_iter, void *stream);
@@ -262,8 +264,8 @@ void luqr_destroy(luqr_factors f);
  *   precision and opts.nrhs_max need (luqr_workspace_bytes) exceeds
  *   LUQR_NOALLOC_SCRATCH_BYTES; for example N = 2048 fits in FP64 at
  *   n_b = 128 and in FP32 at n_b = 256.
- *   Waits for `stream` (to read the decision sequence, after each refinement
- *   residual and before returning the status), like luqr_solve_refined.
+ *   Only enqueues when status is NULL (then it can be captured in a HIP
+ *   graph); with a status it waits for `stream` before filling it.
  *   Every call on one GPU uses that GPU's one buffer, which keeps the last
  *   call's contents: calls that overlap on one GPU (from several host threads
  *   or streams) race and must be serialized by the caller. */

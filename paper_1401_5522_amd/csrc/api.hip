@@ -21,16 +21,16 @@ struct luqr_factors_s {
     luqr_opts o;
     int nsteps;
     std::vector<hipEvent_t> ev;  // LUQR_NPHASE + 1 per step when opts.timing is set
-    std::vector<int> hdec;       // decision sequence, read once by the first solve
+    std::vector<int> hdec;       // decision sequence, read once by the first GMRES refinement
     Side side{nullptr, nullptr, nullptr};  // lookahead stream and events (unless opts.no_lookahead)
 };
 
 static int hip_rc(hipError_t e) { return e == hipSuccess ? 0 : LUQR_ERR_HIP - (int)e; }
 
 
-// The decisions are final once the factorization is done; the first solve
-// waits for it once and keeps them, so each later solve launches only the
-// kernels of the branch every step took.
+// The decisions are final once the factorization is done; GMRES refinement
+// (which waits on the host anyway) reads them once and keeps them, so its
+// solves launch only the kernels of the branch every step took.
 static int host_decisions(luqr_factors f, const int **out) {
     if (f->hdec.empty()) {
         std::vector<int> d((size_t)f->L.n);
@@ -147,19 +147,19 @@ extern "C" int luqr_solve(luqr_factors f, int64_t nrhs, double *dB, int64_t ldb,
     if (ldb < f->L.N) return -4;
     if (f->nsteps < f->L.n) return LUQR_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
-    const int *hdec;
-    int rc = host_decisions(f, &hdec);
-    if (rc) return rc;
     SolveArgs s = solve_args(f->L, f->base, (int)nrhs, nullptr);
     (void)hipGetLastError();
     k_rhs_in<<<nblk(f->L.Np * nrhs), WG, 0, st>>>(dB, ldb, s.Y, f->L.N, f->L.Np, (int)nrhs, nullptr);
-    f->ops->solve(f->c, f->L, s, hdec, st);
+    f->ops->solve(f->c, f->L, s, nullptr, st);  // both branches per step, decided on the device
     k_rhs_out<<<nblk(f->L.N * nrhs), WG, 0, st>>>(s.X, dB, ldb, f->L.N, f->L.Np, (int)nrhs);
     return hip_rc(hipGetLastError());
 }
 
 // The body of luqr_solve_refined over a factorization in the workspace at
-// `base` whose decision sequence the host holds in hdec.
+// `base`.  hdec: the decision sequence if the host holds it, else nullptr.
+// Every iteration is enqueued; once the device test has passed, the kernels
+// of the later ones return at once (they read the convergence flag), so
+// nothing waits on the host.
 static int refined_solve(const Layout &L, const Ctx &c, const Ops *ops, void *base, const int *hdec,
                          const double *dA, int64_t lda, int64_t nrhs, const double *dB, int64_t ldb, double *dX,
                          int64_t ldx, int32_t max_iter, hipStream_t st) {
@@ -191,12 +191,6 @@ static int refined_solve(const Layout &L, const Ctx &c, const Ops *ops, void *ba
                                                   it == 0 ? apart : nullptr, Xk, R, norms, conv);
         k_ir_check<<<1, 64, 0, st>>>(norms, nq, L.N, conv, c.st, last ? 1 : 0);
         if (last) break;
-        // stop enqueuing once the test has passed (one small read per iteration)
-        int done = 0;
-        hipError_t ce2 = hipMemcpyAsync(&done, conv, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (ce2 == hipSuccess) ce2 = hipStreamSynchronize(st);
-        if (ce2 != hipSuccess) return hip_rc(ce2);
-        if (done) break;
         SolveArgs sr = solve_args(L, base, nq, conv);
         // rows N..Np-1 of R are never written by the residual kernels: copy
         // only the first N rows and zero the padding
@@ -222,10 +216,7 @@ extern "C" int luqr_solve_refined(luqr_factors f, const double *dA, int64_t lda,
     if (ldx < f->L.N) return -8;
     if (max_iter < 0) return -9;
     if (f->nsteps < f->L.n) return LUQR_ERR_UNSUPPORTED;
-    const int *hdec;
-    int rc0 = host_decisions(f, &hdec);
-    if (rc0) return rc0;
-    return refined_solve(f->L, f->c, f->ops, f->base, hdec, dA, lda, nrhs, dB, ldb, dX, ldx, max_iter,
+    return refined_solve(f->L, f->c, f->ops, f->base, nullptr, dA, lda, nrhs, dB, ldb, dX, ldx, max_iter,
                          (hipStream_t)stream);
 }
 
@@ -543,15 +534,10 @@ extern "C" int luqr_solve_noalloc(int64_t N, const double *dA, int64_t lda, cons
     ops->factor(c, L, dA, lda, oo, (int)L.n, st, nullptr, nullptr);
     rc = hip_rc(hipGetLastError());
     if (rc) return rc;
-    int hdec[NOALLOC_MAX_STEPS];
-    hipError_t e = hipStreamSynchronize(st);
-    if (e == hipSuccess)
-        e = hipMemcpy(hdec, (char *)base + L.off_dec, (size_t)L.n * sizeof(int), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_rc(e);
-    rc = refined_solve(L, c, ops, base, hdec, dA, lda, nrhs, dB, ldb, dX, ldx, max_iter, st);
+    rc = refined_solve(L, c, ops, base, nullptr, dA, lda, nrhs, dB, ldb, dX, ldx, max_iter, st);
     if (rc || !status) return rc;
     DevStatus d;
-    e = hipStreamSynchronize(st);
+    hipError_t e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = hipMemcpy(&d, (char *)base + L.off_status, sizeof(d), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_rc(e);
     status->info = d.info;

@@ -124,8 +124,10 @@ struct Eng {
         if (side) (void)hipStreamWaitEvent(st, side->eb, 0);  // join: the factorization ends on st
     }
 
-    // hdec: the decision sequence on the host; only the chosen branch of each
-    // step is launched (the kernels check the device copy as well).
+    // hdec: the decision sequence on the host, if the caller has it: only the
+    // chosen branch of each step is launched.  nullptr: both branches are
+    // launched and the kernels of the other one return at once (they read the
+    // decision on the device), so the solve needs no host round trip.
     static void solve(const Ctx &c, const Layout &L, SolveArgs s, const int *hdec, hipStream_t st) {
         const int n = (int)c.n;
         const unsigned ch = (unsigned)((s.nrhs + rq<NB>() - 1) / rq<NB>());
@@ -143,11 +145,12 @@ struct Eng {
         }
         for (int k = 0; k < n && !wave; ++k) {
             const int rest = n - k - 1;
-            if (hdec[k] == 1) {
+            if (!hdec || hdec[k] == 1) {
                 if (c.dcount(k) > 1) k_fwd_dswap<NB><<<dim3(1, (unsigned)((s.nrhs + 15) / 16)), WG, 0, st>>>(c, s, k);
                 k_fwd_lu_a<NB><<<dim3(RPT, ch), WG, 0, st>>>(c, s, k);
                 if (rest > 0) k_fwd_lu_b<NB, S><<<dim3(rest * RPT, ch), WG, 0, st>>>(c, s, k);
-            } else {
+            }
+            if (!hdec || hdec[k] == 0) {
                 const QrTree tr(n, k, c.qtree);
                 if (rest > 0) k_fwd_qr_g<NB, S><<<dim3(rest * qs<NB>(), ch), WG, 0, st>>>(c, s, k);
                 k_fwd_qr_chain<NB, S><<<dim3(tr.G, ch), chain_wg<NB, S>(), 0, st>>>(c, s, k);

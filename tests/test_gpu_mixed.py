@@ -238,3 +238,38 @@ def test_lu_contraction_accuracy(gpu, prec):
     assert st.ir_converged == 1, (st.ir_iters, st.ir_eta)
     assert st.ir_eta <= target and eta(A, x, b) <= target
     assert st.ir_iters <= 8, (st.ir_iters, st.ir_eta)
+
+
+@pytest.mark.parametrize("nb,prec", [(256, "fp32"), (64, "fp64")])
+def test_refined_solve_captured_in_a_graph(gpu, nb, prec):
+    """luqr_solve and luqr_solve_refined only enqueue (the decisions and the
+    convergence test are read on the device), so both can be captured in a
+    HIP graph.  Each replay, with eager work and synchronizations between
+    replays, must give the eager result bit for bit."""
+    import torch
+    N = 1024
+    A = torch.from_numpy(inputs.usv(N, 1e2, seed=(130, N))).cuda()
+    b = torch.from_numpy(inputs.rhs(N, 1, seed=(131, N)).reshape(N, 1)).cuda()
+    f = gpu.factor(A, nb, criterion="max", alpha=50.0, precision=prec)
+    torch.cuda.synchronize()
+    x_eager = f.solve_refined(A, b, max_iter=6).clone()
+    y_eager = f.solve(b.clone()).clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    bs = b.clone()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            xg = f.solve_refined(A, b, max_iter=6)
+            yg = f.solve(bs)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        bs.copy_(b)
+        (A @ b).sum().item()  # eager work between the replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(xg, x_eager), rep
+        assert torch.equal(yg, y_eager), rep
+    st = f.status()
+    assert st.ir_converged == 1 and st.watchdog == 0
