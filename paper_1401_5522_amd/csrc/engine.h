@@ -12,6 +12,25 @@
 
 namespace lq {
 
+// Panel of variant A2 (Sec. 2.3): GEQRT of the FP64 copy W_k of A_kk by the
+// QR step's producers in FP64 (workgroups 0..nb/IB-1), T's diagonal blocks
+// into the Dinv_k slot until k_a2_commit; publishes the flags of tile k for
+// the QR step that may continue from it.  The criterion's tile norms run
+// beside it (the workgroups after the producers, tile k+1.. in order).
+template <int NB, class S>
+__global__ __launch_bounds__(WG) void k_a2_geqrt(Ctx c, int k) {
+    __shared__ __attribute__((aligned(16))) char smem[qr_lds<NB, P64>()];
+    if ((int)blockIdx.x >= qr_pw<NB>()) {
+        tile_norms<NB, S>(c, k, k + 1 + (int)blockIdx.x - qr_pw<NB>(), (double *)smem);
+        return;
+    }
+    QrChain ch;  // the GEQRT unit of tile k alone
+    ch.top = k; ch.mfirst = k + 1; ch.end = k + 1; ch.epoch = qr_epoch(k, 0);
+    ch.geqrt = true; ch.tt = false;
+    qr_producer<NB, P64, false, false>(c, k, ch, (int)blockIdx.x, smem, false, c.W + (size_t)k * NB * NB,
+                                       c.Dinv + (size_t)k * NB * NB);
+}
+
 // Lookahead resources owned by a factorization handle: a second stream (default
 // priority) and two events that order it against the caller's stream.
 struct Side {
@@ -55,21 +74,22 @@ struct Eng {
         for (int k = 0; k < nsteps; ++k) {
             const int rest = n - k - 1;
             if (ev) (void)hipEventRecord(ev[E * k + 0], st);
-            if (rest > 0) k_panel_norms<NB, S><<<rest, WG, 0, st>>>(c, k);
+            // the tile norms of the criterion run as extra workgroups of the
+            // launch that factors the diagonal tile
             if (c.a2) {
                 // variant A2: GEQRT of A_kk (FP64, on a working copy), Q^T, the
                 // rounded factors into the tile, R^{-1}
                 k_a2_copy<NB, S><<<NB * NB / (4 * WG), WG, 0, st>>>(c, k);
-                k_a2_geqrt<NB><<<qr_pw<NB>(), WG, 0, st>>>(c, k);
+                k_a2_geqrt<NB, S><<<qr_pw<NB>() + rest, WG, 0, st>>>(c, k);
                 k_a2_qt<NB><<<NB / 16, WG, 0, st>>>(c, k);
                 k_a2_commit<NB, S><<<NB * NB / (4 * WG), WG, 0, st>>>(c, k);
                 k_a2_rinv<NB><<<NB / 4, WG, 0, st>>>(c, k);
             } else {
                 if constexpr (NB <= 256) {
-                    if (c.dcount(k) > 1) k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);  // up to 512 stacked rows
-                    else k_panel_getrf<NB, S, 1><<<1, WG, 0, st>>>(c, k);
+                    if (c.dcount(k) > 1) k_panel_getrf<NB, S, 2><<<1 + rest, WG, 0, st>>>(c, k);  // up to 512 stacked rows
+                    else k_panel_getrf<NB, S, 1><<<1 + rest, WG, 0, st>>>(c, k);
                 } else {
-                    k_panel_getrf<NB, S, 2><<<1, WG, 0, st>>>(c, k);
+                    k_panel_getrf<NB, S, 2><<<1 + rest, WG, 0, st>>>(c, k);
                 }
                 k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
             }

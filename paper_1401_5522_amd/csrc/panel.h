@@ -478,9 +478,10 @@ LQ_DEV void getrf_core(const Ctx &c, int k, void *smem) {
 // Column sums and column maxima of |A_ik| (one workgroup per tile).  A wave
 // takes columns w, w + 4, ...; CPW of them are loaded before any is reduced,
 // so that enough loads are in flight to cover the memory latency.
+// cs: NB doubles of LDS (the caller's: this runs inside launches whose other
+// workgroups need all of theirs).
 template <int NB, class S>
-LQ_DEV void tile_norms(const Ctx &c, int k, int i) {
-    __shared__ double cs[NB];
+LQ_DEV void tile_norms(const Ctx &c, int k, int i, double *cs) {
     const int l = lane_id(), w = wave_id();
     const S *A = (const S *)c.At + c.toff(i, k);
     constexpr int RPL = NB >= 64 ? NB / 64 : 1;  // rows per lane
@@ -515,20 +516,21 @@ LQ_DEV void tile_norms(const Ctx &c, int k, int i) {
 
 // Norms of the tiles below the diagonal in tile column k, one workgroup per
 // tile (the tiles of a diagonal domain are measured after its elimination).
-template <int NB, class S>
-__global__ __launch_bounds__(WG) void k_panel_norms(Ctx c, int k) {
-    const int i = k + 1 + (int)blockIdx.x;
-    if (!c.indom(k, i)) tile_norms<NB, S>(c, k, i);
-}
 
 // GEPP of the diagonal tile (RPT = 1) or of the stacked diagonal domain and
-// of 512-row tiles (RPT = 2): one workgroup, launched apart from the norms so
-// that its LDS and register needs do not fall on every tile's workgroup; the
-// tile variant is held to half a SIMD's registers, so that it fits on a compute
-// unit beside a trailing-update workgroup of the previous step.
+// of 512-row tiles (RPT = 2) in workgroup 0; the tile norms of the criterion
+// (workgroups 1.., tile k + blockIdx.x), which do not depend on it, run beside
+// it in the same launch, so they cost nothing on the step's critical path.
+// The tile variant is held to half a SIMD's registers, so that it fits on a
+// compute unit beside a trailing-update workgroup of the previous step.
 template <int NB, class S, int RPT>
 __global__ __launch_bounds__(WG, RPT == 1 ? 2 : 1) void k_panel_getrf(Ctx c, int k) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(GetrfSmem<NB, RPT>)];
+    if (blockIdx.x > 0) {
+        const int i = k + (int)blockIdx.x;
+        if (!c.indom(k, i)) tile_norms<NB, S>(c, k, i, (double *)smem);
+        return;
+    }
     getrf_core<NB, S, RPT>(c, k, smem);
 }
 

@@ -783,20 +783,6 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     }
 }
 
-// Panel of variant A2 (Sec. 2.3): GEQRT of the FP64 copy W_k of A_kk by the
-// QR step's producers in FP64 (grid nb/IB), T's diagonal blocks into the
-// Dinv_k slot until k_a2_commit; publishes the flags of tile k for the QR
-// step that may continue from it.
-template <int NB>
-__global__ __launch_bounds__(WG) void k_a2_geqrt(Ctx c, int k) {
-    __shared__ __attribute__((aligned(16))) char smem[qr_lds<NB, P64>()];
-    QrChain ch;  // the GEQRT unit of tile k alone
-    ch.top = k; ch.mfirst = k + 1; ch.end = k + 1; ch.epoch = qr_epoch(k, 0);
-    ch.geqrt = true; ch.tt = false;
-    qr_producer<NB, P64, false, false>(c, k, ch, (int)blockIdx.x, smem, false, c.W + (size_t)k * NB * NB,
-                                       c.Dinv + (size_t)k * NB * NB);
-}
-
 // ---------------------------------------------------------------------------
 // Completion of the nb x nb compact-WY factors of a QR step's panel tiles
 // (needed by the solve only).  With V = [V_0 .. V_{B-1}] split in IB-column
