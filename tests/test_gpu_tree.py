@@ -113,3 +113,39 @@ def test_tree_lookahead_bit_identical(gpu):
     assert np.array_equal(fa.decisions()[0], fb.decisions()[0])
     assert np.array_equal(fa.export()[0].cpu().numpy(), fb.export()[0].cpu().numpy())
     assert np.array_equal(fa.solve(dev(b)).cpu().numpy(), fb.solve(dev(b)).cpu().numpy())
+
+
+def test_tree_with_domain_and_estimate(O, gpu):
+    """The tree changes only the QR steps, the domain and the estimate only the
+    LU attempt and the criterion: the combinations against the oracle's."""
+    A = inputs.gaussian(384, seed=(830,))
+    b = inputs.rhs(384, seed=(831,))
+    for kw in (dict(domain=2), dict(estimate=True)):
+        f = gpu.factor(dev(A), 64, criterion="max", alpha=60.0, tree=2, **kw)
+        o = O.factor(A, 64, "max", 60.0, tree=2, **kw)
+        dec = f.decisions()[0]
+        for k in range(len(o.dec)):
+            if abs(o.margin[k]) <= BAND:
+                break
+            assert dec[k] == o.dec[k], (kw, k)
+        else:
+            x = f.solve(dev(b)).cpu().numpy()
+            xo = o.solve(b)
+            assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo), kw
+        assert f.status().watchdog == 0
+
+
+@pytest.mark.parametrize("precision,tree,variant", [("fp32", 2, 1), ("bf16", 1, 1), ("bf16", 0, 2), ("fp32", 2, 2)])
+def test_nb512_tree_and_a2_refined(gpu, precision, tree, variant):
+    """n_b = 512 (one QR-step workgroup per compute unit) with trees and with
+    variant A2 in FP32/BF16 storage, refined to the FP64 target."""
+    N = 3072
+    A = inputs.usv(N, 1e1, seed=(832, tree, variant))
+    b = inputs.rhs(N, seed=(833,))
+    f = gpu.factor(dev(A), 512, criterion="max", alpha=1.0, precision=precision, tree=tree, variant=variant)
+    x = f.solve_refined(dev(A), dev(b), max_iter=30).cpu().numpy()
+    st = f.status()
+    assert st.watchdog == 0
+    assert st.ir_converged == 1, (st.ir_iters, st.ir_eta)
+    eta = np.linalg.norm(A @ x - b, np.inf) / (np.abs(A).sum(1).max() * np.abs(x).max() + np.abs(b).max())
+    assert eta <= N * 1e-16, eta
