@@ -116,7 +116,7 @@ struct Eng {
                 const QrTree tr(n, k, c.qtree);
                 const int mode = c.a2 ? QR_REST : QR_FULL;
                 const unsigned per = qr_pw<NB>() + rest * qr_spc<NB>();
-                k_qr_step<NB, P, false><<<tr.G * per, WG, 0, st>>>(c, k, mode, 0);
+                k_qr_step<NB, P, false><<<tr.G * per + qr_keepers<NB, P>(n, k, tr.G), WG, 0, st>>>(c, k, mode, 0);
                 for (int d = 1; d < tr.G; d *= 2)
                     k_qr_step<NB, P, true><<<tr.npairs(d) * per, WG, 0, st>>>(c, k, mode, d);
             }

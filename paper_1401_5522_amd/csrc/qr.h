@@ -653,6 +653,26 @@ template <int NB, int P> constexpr int qr_occ() { return qr_step_lds<NB, P>() <=
 // workgroups per chain, so they are dispatched before any consumer and a
 // consumer never waits on an unscheduled producer), then per chain one
 // consumer per 64-column strip of every trailing tile column.
+// Keepers (a single chain, two workgroups per CU, a grid that doubles up at
+// least 2 nb/IB CUs but still fits at two per CU): the workgroups numbered
+// QR_CUS + b.  Dispatch in order fills every CU once before it doubles any,
+// so on an otherwise idle GPU workgroup QR_CUS + b lands beside producer b.
+// The keeper only waits for that producer's last unit, which keeps the
+// producer's CU for it: a consumer beside it slows the producer, and the
+// producer chain paces every consumer.  The consumers it displaces double up
+// with other consumers, so it pays only once enough of them do anyway
+// (measured: slower at 16 doubled workgroups, faster from about 40).  (If
+// keepers land elsewhere, they only wait.)  Their number in the groups'
+// launch (d = 0) of step k (0 or nb/IB):
+constexpr int QR_CUS = 256;
+template <int NB, int P> LQ_HD int qr_keepers(int64_t n, int k, int nch) {
+    const int all = qr_pw<NB>() + ((int)n - k - 1) * qr_spc<NB>();
+    return (qr_occ<NB, P>() == 2 && nch == 1 && all >= QR_CUS + 2 * qr_pw<NB>() &&
+            all + qr_pw<NB>() <= 2 * QR_CUS)
+               ? qr_pw<NB>()
+               : 0;
+}
+
 template <int NB, int P, bool TT>
 __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k, int mode, int d) {
     if (c.dec[k] != 0) return;
@@ -672,7 +692,19 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
         return;
     }
     if (cps == 0) return;
-    const int cidx = (int)blockIdx.x - nch * qr_pw<NB>();
+    int cidx = (int)blockIdx.x - nch * qr_pw<NB>();
+    const int nkeep = d == 0 ? qr_keepers<NB, P>(c.n, k, nch) : 0;  // as the host sized the groups' launch
+    if (nkeep > 0 && (int)blockIdx.x >= QR_CUS) {
+        const int b = (int)blockIdx.x - QR_CUS;
+        if (b < nkeep) {  // a keeper: wait for producer b's last unit
+            if (threadIdx.x == 0) {
+                const QrChain ch = qr_chain(c, k, d, 0);
+                (void)flag_wait(qr_flag(c, ch.end - 1, b), ch.epoch, &c.st->watchdog);
+            }
+            return;
+        }
+        cidx -= nkeep;
+    }
     const QrChain ch = qr_chain(c, k, d, cidx / cps);
     // Consumer: one 64-column strip of trailing tile column j.  The blocks it
     // applies form one sequence s = 0 .. nblocks-1: block b of tile i = t0 +
