@@ -181,7 +181,19 @@ struct Eng {
                 }
             }
         }
-        for (int k = n - 1; k >= 0; --k) {
+        bool bwave = false;
+        if constexpr (NB == 256 && sizeof(S) == 4) {
+            // the back substitution as one wavefront launch; its counters follow
+            // the forward pass's in the QR steps' flags (n * nb/IB ints)
+            const int wch = (s.nrhs + FW_RQ - 1) / FW_RQ;
+            if (wch <= 4) {
+                int *cb = c.flags + (size_t)n * 4;
+                k_fill_int<<<nblk((int64_t)n * wch), WG, 0, st>>>(cb, (int64_t)n * wch, 0);
+                k_bwd_wave<NB, S><<<dim3(n, wch), FW_WG, 0, st>>>(c, s, cb);
+                bwave = true;
+            }
+        }
+        for (int k = n - 1; k >= 0 && !bwave; --k) {
             k_bwd_a<NB><<<dim3(RPT, ch), WG, 0, st>>>(c, s, k);
             if (k > 0) k_bwd_b<NB, S><<<dim3(k * RPT, ch), WG, 0, st>>>(c, s, k);
         }

@@ -573,10 +573,12 @@ template <int MODE> LQ_DEV void fw_rows(FwTile &t, const double *v, int nq, doub
         for (int e = 0; e < 4; ++e) red[(w * nq + q) * 256 + 4 * l + e] = acc[e];
     }
 }
-// The same row products for the FP64 unit-lower L_kk^{-1} (MODE 2; dense:
-// as stored, for variant A2's Q_kk^T), in four passes of 8 columns per wave:
-// lane l holds rows 2l, 2l+1 and 128+2l, 128+2l+1.
-LQ_DEV void fw_rows_linv(const double *M, const double *v, int nq, double *red, bool dense) {
+// The same row products for an FP64 256 x 256 matrix, by MODE: 0 as stored
+// (variant A2's Q_kk^T); 1 upper triangle (the diagonal factor's inverse of
+// the back substitution); 2 unit lower (L_kk^{-1}).  Four passes of 8
+// columns per wave: lane l holds rows 2l, 2l+1 and 128+2l, 128+2l+1.
+template <int MODE>
+LQ_DEV void fw_rows_d(const double *M, const double *v, int nq, double *red) {
     const int w = wave_id(), l = lane_id();
     double acc[FW_RQ][4];
 #pragma unroll
@@ -599,7 +601,9 @@ LQ_DEV void fw_rows_linv(const double *M, const double *v, int nq, double *red, 
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int p = 128 * h + 2 * l + e;
-                    const double x = (dense || p > cc) ? a[j][h][e] : (p == cc ? 1.0 : 0.0);
+                    const double x = MODE == 0 ? a[j][h][e]
+                                     : MODE == 1 ? (p <= cc ? a[j][h][e] : 0.0)
+                                                 : (p > cc ? a[j][h][e] : (p == cc ? 1.0 : 0.0));
 #pragma unroll
                     for (int q = 0; q < FW_RQ; ++q)
                         if (q < nq) acc[q][2 * h + e] += x * v[q * 256 + cc];
@@ -669,7 +673,8 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
         const int *pm = c.perm + (size_t)k * 256;
         for (int e = tid; e < 256 * nq; e += FW_WG) yi[e] = ld((int64_t)k * 256 + pm[e % 256] + (int64_t)(q0 + e / 256) * Np);
         __syncthreads();
-        fw_rows_linv(c.Linv + (size_t)k * 256 * 256, yi, nq, red, c.a2);  // A2: the dense Q_kk^T
+        if (c.a2) fw_rows_d<0>(c.Linv + (size_t)k * 256 * 256, yi, nq, red);  // A2: the dense Q_kk^T
+        else fw_rows_d<2>(c.Linv + (size_t)k * 256 * 256, yi, nq, red);
         __syncthreads();
         for (int e = tid; e < 256 * nq; e += FW_WG) {
             const int q = e / 256, p = e % 256;
@@ -742,6 +747,78 @@ static __global__ __launch_bounds__(FW_WG) void k_fwd_wave(Ctx c, SolveArgs s, i
 
 // Back-substitution, part 1: x_k = D_k^{-1} z_k (D_k = U or R of step k;
 // its FP64 inverse is upper triangular).  grid (nb / RB, rhs chunks).
+// ---------------------------------------------------------------------------
+// The back substitution as one wavefront launch (n_b = 256, 4-byte storage):
+// workgroup b solves tile row k = n-1-b,
+//     x_k = D_k^{-1} (z_k - sum_{j>k} U_kj x_j),
+// with D_k^{-1} the FP64 inverse of the diagonal factor (U or R) and U_kj the
+// stored tiles, taking each x_j (j = n-1 down to k+1) as soon as workgroup
+// n-1-j has published it (cnt[j] = 1, one array per right-hand-side chunk),
+// so the tile products of different rows overlap and only the chain of the
+// last product and the diagonal solve is sequential.  x is written and read
+// with agent-scope atomics, as y in the forward pass; a workgroup waits only
+// on lower-numbered ones, which are dispatched first.
+// ---------------------------------------------------------------------------
+template <int NB, class S>
+static __global__ __launch_bounds__(FW_WG) void k_bwd_wave(Ctx c, SolveArgs s, int *cnt) {
+    static_assert(NB == 256 && sizeof(S) == 4, "wavefront back substitution: n_b = 256, 4-byte storage");
+    if (gated(s.gate)) return;
+    __shared__ double zk[256 * FW_RQ], xv[256 * FW_RQ];
+    __shared__ double red[8 * 256 * FW_RQ];
+    __shared__ int bail;
+    const int n = (int)c.n, k = n - 1 - (int)blockIdx.x, tid = threadIdx.x;
+    const int q0 = blockIdx.y * FW_RQ, nq = min(FW_RQ, s.nrhs - q0);
+    int *cn = cnt + (size_t)blockIdx.y * n;
+    const int64_t Np = (int64_t)n * 256;
+    const float *At = (const float *)c.At;
+    auto gx = [&](int i, int e) { return (int64_t)i * 256 + e % 256 + (int64_t)(q0 + e / 256) * Np; };
+    auto wait = [&](int j) __attribute__((always_inline)) {
+        if (tid == 0) {
+            long spins = 0;
+            bail = 0;
+            while (__hip_atomic_load(cn + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 1) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1L << 27) ||
+                    __hip_atomic_load(&c.st->watchdog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(&c.st->watchdog, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bail = 1;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        return !bail;
+    };
+    auto sum_red = [&](int e) __attribute__((always_inline)) {
+        const int q = e / 256, p = e % 256;
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) t += red[(w * nq + q) * 256 + p];
+        return t;
+    };
+    for (int e = tid; e < 256 * nq; e += FW_WG) zk[e] = s.Z[gx(k, e)];
+    FwTile tu;
+    if (k + 1 < n) tu.load(At + c.toff(k, n - 1));
+    for (int j = n - 1; j > k; --j) {
+        if (!wait(j)) return;
+        for (int e = tid; e < 256 * nq; e += FW_WG)
+            xv[e] = __hip_atomic_load(s.X + gx(j, e), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        fw_rows<0>(tu, xv, nq, red);  // U_kj x_j
+        if (j - 1 > k) tu.load(At + c.toff(k, j - 1));
+        __syncthreads();
+        for (int e = tid; e < 256 * nq; e += FW_WG) zk[e] -= sum_red(e);
+        __syncthreads();
+    }
+    fw_rows_d<1>(c.Dinv + (size_t)k * 256 * 256, zk, nq, red);  // D_k^{-1} (upper triangular)
+    __syncthreads();
+    for (int e = tid; e < 256 * nq; e += FW_WG)
+        __hip_atomic_store(s.X + gx(k, e), sum_red(e), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores of x_k have completed
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(cn + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int NB>
 static __global__ __launch_bounds__(WG) void k_bwd_a(Ctx c, SolveArgs s, int k) {
     if (gated(s.gate)) return;
