@@ -142,9 +142,9 @@ def test_a2_lookahead_bit_identical(gpu):
 @pytest.mark.parametrize("variant", [1, 2])
 def test_wavefront_forward_matches_per_step(gpu, variant):
     """FP32 at n_b = 256 with at most 16 right-hand sides solves through the
-    one-launch wavefront forward pass; 17 take the per-step kernels.  Both are
-    FP64 arithmetic on the same factors, so the first column agrees to
-    rounding (A2: its LU rows take the dense Q_kk^T)."""
+    one-launch wavefront forward pass and back substitution; 17 take the
+    per-step kernels.  Both are FP64 arithmetic on the same factors, so the
+    first column agrees to rounding (A2: its LU rows take the dense Q_kk^T)."""
     import torch
     N, nb = 1536, 256
     A = inputs.usv(N, 1e2, seed=(811,))
