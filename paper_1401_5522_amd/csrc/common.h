@@ -248,7 +248,7 @@ struct Layout {
     int64_t sz_S;  // bytes of a storage element
     size_t off_At, off_Tf, off_gram, off_W, off_Linv, off_Dinv, off_ipiv, off_perm, off_zpiv;
     size_t off_dec, off_s, off_m, off_margin, off_status;
-    size_t off_tnorm, off_away, off_lmax, off_invpart, off_flags, off_scale;
+    size_t off_tnorm, off_away, off_lmax, off_invpart, off_flags, off_eflag, off_scale;
     size_t off_Y, off_Z, off_X, off_R, off_D, off_Xd, off_G, off_part, off_apart, off_rnorm, off_anorm, off_conv;
     size_t off_kry, off_kdots;  // GMRES refinement: KRYLOV_MAX + 2 vectors of Np doubles; dot scratch
     size_t total;
@@ -288,6 +288,7 @@ inline Layout make_layout(int64_t N, int64_t nb, int prec, int nrhs_max, int dst
     L.off_lmax = take(b * 8);
     L.off_invpart = take((b / 16 + 1) * b * 8);
     L.off_flags = take(n * (b / IB) * 4 + 64);
+    L.off_eflag = take(n * 4);
     L.off_scale = take(n * n * 4);
     L.off_WD = take(L.DR > (int64_t)b ? (size_t)L.DR * b * 8 : 8);
     L.off_dperm = take(L.DR > (int64_t)b ? n * (size_t)L.DR * 4 : 8);
@@ -332,6 +333,7 @@ struct Ctx {
     double *lmax;    // column maxima of A_kk before factoring (MUMPS)
     double *invpart; // partial column sums of |A_kk^{-1}| per 64-row block
     int *flags;      // QR-step pipeline: flag[i*(nb/IB) + b] = k+1 once block b of tile i's reflectors is published
+    int *eflag;      // per step k: consumers of tile column k+1 that have written tile (k+1,k+1) in QR step k
     unsigned *tmax;  // per tile: bit pattern of max |a| (BF16 scaling), tile-major index (j*n+i)
     double *WD;      // diagonal domain of the current step: stacked FP64 copy (DR x nb), factored
     int *dperm;      // per step: stacked-row permutation of the domain, (P D)(s,:) = D(dperm[s],:)
@@ -387,7 +389,7 @@ inline Ctx make_ctx(const Layout &L, void *base, int a2 = 0) {
     c.margin = (double *)(b + L.off_margin); c.st = (DevStatus *)(b + L.off_status);
     c.tnorm = (double *)(b + L.off_tnorm); c.away = (double *)(b + L.off_away);
     c.lmax = (double *)(b + L.off_lmax); c.invpart = (double *)(b + L.off_invpart);
-    c.flags = (int *)(b + L.off_flags); c.tmax = (unsigned *)(b + L.off_scale);
+    c.flags = (int *)(b + L.off_flags); c.eflag = (int *)(b + L.off_eflag); c.tmax = (unsigned *)(b + L.off_scale);
     c.WD = (double *)(b + L.off_WD); c.dperm = (int *)(b + L.off_dperm);
     c.N = L.N; c.n = L.n; c.nb = (int)L.nb;
     c.dstride = L.dstride; c.DR = (int)L.DR;

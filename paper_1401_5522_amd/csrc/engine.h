@@ -31,11 +31,41 @@ __global__ __launch_bounds__(WG) void k_a2_geqrt(Ctx c, int k) {
                                        c.Dinv + (size_t)k * NB * NB);
 }
 
+// QR step k of the flat tree (launch d = 0) with the GEPP of step k+1's
+// diagonal tile (GETRF on its FP64 copy, the LU attempt of the next panel) as
+// its last workgroup.  That tile is final once the consumers of tile column
+// k+1 have applied tile k+1's reflectors (two of the step's sequential
+// units), so the GEPP runs beside the rest of the step instead of after it.
+// It waits for their counts in eflag[k]; every other workgroup waits only on
+// lower-numbered ones, and this one is numbered last, so dispatch order still
+// guarantees progress.  Its LDS is the larger of the two routines'.
+template <int NB, int P> constexpr int qr_ep_lds() {
+    return qr_step_lds<NB, P>() > (int)sizeof(GetrfSmem<NB, 1>) ? qr_step_lds<NB, P>() : (int)sizeof(GetrfSmem<NB, 1>);
+}
+template <int NB, int P> constexpr int qr_ep_occ() { return qr_ep_lds<NB, P>() <= 80 * 1024 ? 2 : 1; }
+
+template <int NB, int P>
+__global__ __launch_bounds__(WG, (qr_ep_occ<NB, P>())) void k_qr_step_ep(Ctx c, int k, int mode) {
+    static_assert(NB <= 256, "the tile variant of the GEPP");
+    if (c.dec[k] != 0) return;
+    __shared__ __attribute__((aligned(16))) char smem[qr_ep_lds<NB, P>()];
+    if (blockIdx.x + 1 < gridDim.x) {
+        qr_step_body<NB, P, false>(c, k, mode, 0, 1, smem);
+        return;
+    }
+    __shared__ int ready;
+    if (threadIdx.x == 0) ready = flag_wait(&c.eflag[k], qr_spc<NB>(), &c.st->watchdog);
+    __syncthreads();
+    if (!ready) return;
+    fence_acquire();
+    getrf_core<NB, typename Tr<P>::S, 1>(c, k + 1, smem);
+}
+
 // Lookahead resources owned by a factorization handle: a second stream (default
 // priority) and two events that order it against the caller's stream.
 struct Side {
     hipStream_t st;
-    hipEvent_t ea, eb;
+    hipEvent_t ea, eb, el;
 };
 
 struct Ops {
@@ -58,21 +88,31 @@ struct Eng {
     // side->st once step k's critical part (LU: Eliminate/Apply and the update
     // of column k+1; QR: the QR step) is done (event ea), so that step k+1's
     // panel factor, norms and decision run meanwhile on st; step k+1's branch
-    // kernels wait for it (event eb).  The panel of step k+1 reads only tile
-    // column k+1, which the critical part has finished, and writes only its
-    // own per-step buffers.
+    // kernels wait for the LU update (event el), while a QR step's R^-1 and
+    // full T, which read only tile column k and write only its own buffers,
+    // may still run (the factorization ends by waiting for all of it, event
+    // eb).  The panel of step k+1 reads only tile column k+1, which the
+    // critical part has finished, and writes only its own per-step buffers.
+    // Early GEPP (flat tree, variant A1, step k+1 without a domain, nb <=
+    // 256): the QR step runs as k_qr_step_ep, and step k+1's panel launch
+    // leaves the GEPP out when step k was a QR step.
     static void factor(const Ctx &c, const Layout &L, const double *A, int64_t lda, const luqr_opts &o, int nsteps,
                        hipStream_t st, hipEvent_t *ev, const Side *side) {
         const int n = (int)c.n;
         k_status_reset<<<1, 64, 0, st>>>(c.st);
         k_fill_int<<<nblk((int64_t)n * (NB / IB)), WG, 0, st>>>(c.flags, (int64_t)n * (NB / IB), 0);
+        k_fill_int<<<nblk(n), WG, 0, st>>>(c.eflag, n, 0);
         k_fill_int<<<nblk(n), WG, 0, st>>>(c.dec, n, -1);
         k_fill_u32<<<nblk((int64_t)n * n), WG, 0, st>>>(c.tmax, (int64_t)n * n);
         k_to_tiles<S><<<nblk(L.Np * L.Np), WG, 0, st>>>(A, lda, c.N, c.n, NB, (S *)c.At);
         constexpr int B = NB < 64 ? NB : 64;
         constexpr int E = LUQR_NPHASE + 1;
+        auto early_ok = [&](int k) {  // step k's GEPP may run inside QR step k-1
+            return NB <= 256 && k > 0 && k < nsteps && !c.a2 && c.qtree == 0 && c.dcount(k) == 1;
+        };
         for (int k = 0; k < nsteps; ++k) {
             const int rest = n - k - 1;
+            const int pe = early_ok(k) ? 1 : 0;
             if (ev) (void)hipEventRecord(ev[E * k + 0], st);
             // the tile norms of the criterion run as extra workgroups of the
             // launch that factors the diagonal tile
@@ -86,10 +126,10 @@ struct Eng {
                 k_a2_rinv<NB><<<NB / 4, WG, 0, st>>>(c, k);
             } else {
                 if constexpr (NB <= 256) {
-                    if (c.dcount(k) > 1) k_panel_getrf<NB, S, 2><<<1 + rest, WG, 0, st>>>(c, k);  // up to 512 stacked rows
-                    else k_panel_getrf<NB, S, 1><<<1 + rest, WG, 0, st>>>(c, k);
+                    if (c.dcount(k) > 1) k_panel_getrf<NB, S, 2><<<1 + rest, WG, 0, st>>>(c, k, 0);  // up to 512 stacked rows
+                    else k_panel_getrf<NB, S, 1><<<1 + rest, WG, 0, st>>>(c, k, pe);
                 } else {
-                    k_panel_getrf<NB, S, 2><<<1 + rest, WG, 0, st>>>(c, k);
+                    k_panel_getrf<NB, S, 2><<<1 + rest, WG, 0, st>>>(c, k, 0);
                 }
                 k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
             }
@@ -102,7 +142,7 @@ struct Eng {
             a.seed = o.seed;
             k_panel_decide<NB><<<1, WG, 0, st>>>(c, k, a);
             if (ev) (void)hipEventRecord(ev[E * k + 1], st);
-            if (side && k > 0) (void)hipStreamWaitEvent(st, side->eb, 0);  // step k-1's bulk work
+            if (side && k > 0) (void)hipStreamWaitEvent(st, side->el, 0);  // step k-1's LU update
             if (c.dcount(k) > 1) k_domain_swap<NB, P><<<(unsigned)rest * (NB / DSW_CW), WG, 0, st>>>(c, k);
             k_lu_apply<NB, P><<<1 + 2 * rest * (NB / lu_rb<NB>()), WG, 0, st>>>(c, k);
             if (ev) (void)hipEventRecord(ev[E * k + 2], st);
@@ -116,7 +156,13 @@ struct Eng {
                 const QrTree tr(n, k, c.qtree);
                 const int mode = c.a2 ? QR_REST : QR_FULL;
                 const unsigned per = qr_pw<NB>() + rest * qr_spc<NB>();
-                k_qr_step<NB, P, false><<<tr.G * per + qr_keepers<NB, P>(n, k, tr.G), WG, 0, st>>>(c, k, mode, 0);
+                const unsigned grid = tr.G * per + qr_keepers<NB, P>(n, k, tr.G);
+                if constexpr (NB <= 256) {
+                    if (early_ok(k + 1)) k_qr_step_ep<NB, P><<<grid + 1, WG, 0, st>>>(c, k, mode);
+                    else k_qr_step<NB, P, false><<<grid, WG, 0, st>>>(c, k, mode, 0);
+                } else {
+                    k_qr_step<NB, P, false><<<grid, WG, 0, st>>>(c, k, mode, 0);
+                }
                 for (int d = 1; d < tr.G; d *= 2)
                     k_qr_step<NB, P, true><<<tr.npairs(d) * per, WG, 0, st>>>(c, k, mode, d);
             }
@@ -127,6 +173,7 @@ struct Eng {
                 (void)hipStreamWaitEvent(side->st, side->ea, 0);
                 sb = side->st;
                 if (rest > 1) k_lu_update<NB, P><<<(unsigned)rest * (rest - 1) * PER * PER, WG, 0, sb>>>(c, k, k + 2);
+                (void)hipEventRecord(side->el, sb);
             }
             // QR steps: R_kk after every TSQRT (A2's panel inverted the GEQRT's R for the criterion)
             k_qr_rinv<NB, S><<<NB / 4, WG, 0, sb>>>(c, k);

@@ -514,23 +514,24 @@ LQ_DEV void tile_norms(const Ctx &c, int k, int i, double *cs) {
     }
 }
 
-// Norms of the tiles below the diagonal in tile column k, one workgroup per
-// tile (the tiles of a diagonal domain are measured after its elimination).
-
 // GEPP of the diagonal tile (RPT = 1) or of the stacked diagonal domain and
 // of 512-row tiles (RPT = 2) in workgroup 0; the tile norms of the criterion
-// (workgroups 1.., tile k + blockIdx.x), which do not depend on it, run beside
+// (workgroups 1.., tile k + blockIdx.x; the tiles of a diagonal domain are
+// measured after its elimination), which do not depend on it, run beside
 // it in the same launch, so they cost nothing on the step's critical path.
 // The tile variant is held to half a SIMD's registers, so that it fits on a
 // compute unit beside a trailing-update workgroup of the previous step.
+// early = 1: after a QR step k-1 the tile's GEPP ran inside that step (its
+// last workgroup), so workgroup 0 has nothing to do.
 template <int NB, class S, int RPT>
-__global__ __launch_bounds__(WG, RPT == 1 ? 2 : 1) void k_panel_getrf(Ctx c, int k) {
+__global__ __launch_bounds__(WG, RPT == 1 ? 2 : 1) void k_panel_getrf(Ctx c, int k, int early) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(GetrfSmem<NB, RPT>)];
     if (blockIdx.x > 0) {
         const int i = k + (int)blockIdx.x;
         if (!c.indom(k, i)) tile_norms<NB, S>(c, k, i, (double *)smem);
         return;
     }
+    if (early && c.dec[k - 1] == 0) return;
     getrf_core<NB, S, RPT>(c, k, smem);
 }
 

@@ -673,15 +673,18 @@ template <int NB, int P> LQ_HD int qr_keepers(int64_t n, int k, int nch) {
                : 0;
 }
 
+// sig (flat tree, d = 0): each consumer of tile column k+1 adds one to
+// eflag[k] once it has written its strip of tile (k+1, k+1), which no later
+// block of the step touches, so that the GEPP of step k+1's panel can start
+// on that tile while the rest of the step runs (qr_spc strips in all).
+// smem: qr_step_lds bytes.
 template <int NB, int P, bool TT>
-__global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k, int mode, int d) {
-    if (c.dec[k] != 0) return;
+LQ_DEV void qr_step_body(const Ctx &c, int k, int mode, int d, int sig, char *smem) {
     typedef typename Tr<P>::S S;
     typedef typename Tr<P>::acc acc_t;
     constexpr int VB = qr_vblk<NB>();
     constexpr int NBLK = NB / IB;
     constexpr bool PRE = false;  // bulk operand loads would exceed the registers at nb >= 256
-    __shared__ __attribute__((aligned(16))) char smem[qr_step_lds<NB, P>()];
     const QrTree tr(c.n, k, c.qtree);
     const int nch = d == 0 ? tr.G : tr.npairs(d);
     const int cps = ((int)c.n - k - 1) * qr_spc<NB>();  // consumers per chain
@@ -735,6 +738,7 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
     S *const topc = Akj + (col0 + i16) * NB;  // this lane's column of A_top,j for the TSMQR blocks
     const int t0 = ch.geqrt ? ch.top : ch.mfirst;
     const int nblocks = (ch.end - t0) * NBLK;
+    const int spub = (sig && !TT && ch.top == k && j == k + 1) ? (k + 1 - t0) * NBLK + NBLK - 1 : -1;
     auto vtile = [&](int s) { return At + c.toff(t0 + s / NBLK, k); };
     auto ttile = [&](int s) { return Tq + c.tqoff(t0 + s / NBLK, k); };
     auto flag_of = [&](int s) { return qr_flag(c, t0 + s / NBLK, s % NBLK); };
@@ -791,6 +795,7 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
                 if (i + 1 < ch.end) load_bot(At + c.toff(i + 1, j));
             }
         }
+        if (s == spub) fence_release();  // this strip of tile (k+1, k+1) before the count
         if (has_next) {
             S *Yn = Y0 + (cur ^ 1) * VB, *Tn = T0 + (cur ^ 1) * (IB * IB);
             if constexpr (TT) stage_store<NB, S, 2>(nx, ((s + 1) % NBLK) * IB, Yn, Tn);
@@ -812,7 +817,15 @@ __global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k,
             inval[s & 1] = inv;
         }
         __syncthreads();
+        if (s == spub && tid == 0) __hip_atomic_fetch_add(&c.eflag[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+template <int NB, int P, bool TT>
+__global__ __launch_bounds__(WG, (qr_occ<NB, P>())) void k_qr_step(Ctx c, int k, int mode, int d) {
+    if (c.dec[k] != 0) return;
+    __shared__ __attribute__((aligned(16))) char smem[qr_step_lds<NB, P>()];
+    qr_step_body<NB, P, TT>(c, k, mode, d, 0, smem);
 }
 
 // ---------------------------------------------------------------------------
