@@ -147,7 +147,7 @@ def lu_update_flops(n, nb, dec):
     return float(np.sum((dec == 1) * 2.0 * r * r) * nb ** 3)
 
 
-KERNEL_SOURCES = ("qr.h", "common.h", "mma.h")
+KERNEL_SOURCES = ("qr.h", "common.h", "mma.h", "engine.h", "panel.h")  # k_qr_step_ep: engine.h, its GEPP: panel.h
 
 
 def measured_traffic(kernel, N, prec):

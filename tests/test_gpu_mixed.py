@@ -162,6 +162,35 @@ def test_lookahead_is_a_pure_reordering(gpu, prec, alpha):
     assert np.array_equal(F0, F1)
 
 
+def test_early_panel_lookahead_alternating(gpu):
+    """FP32 at n_b = 256 with lookahead: each QR step's last workgroup
+    factors the next diagonal tile once the step's consumers have finished
+    it, and the next step's branch waits only for the LU update, not for the
+    QR step's R^-1 and T.  LU and QR steps alternate over 32 tiles; the
+    factors, pivots, decisions and refined solution equal the strictly
+    ordered run's bit for bit, and the refined solve reaches the FP64
+    target."""
+    import torch
+    N, nb = 8192, 256
+    A = inputs.usv(N, 1e2, seed=(117,))
+    b = inputs.rhs(N, seed=(118,))
+    seq = np.array([1, 0] * 16, np.int8)
+    runs = []
+    for la in (False, True):
+        f = gpu.factor(torch.from_numpy(np.asfortranarray(A)).cuda(), nb, criterion="forced", forced=seq,
+                       precision="fp32", lookahead=la)
+        F, ipiv = f.export()
+        x = f.solve_refined(torch.from_numpy(np.asfortranarray(A)).cuda(), torch.from_numpy(b).cuda(),
+                            max_iter=30).cpu().numpy()
+        st = f.status()
+        assert st.watchdog == 0 and st.ir_converged == 1, (la, st.watchdog, st.ir_iters)
+        runs.append((F.cpu().numpy(), ipiv, f.decisions()[0], x))
+    (F0, p0, d0, x0), (F1, p1, d1, x1) = runs
+    assert np.array_equal(d0, seq) and np.array_equal(d1, seq)
+    assert (p0 == p1).all() and np.array_equal(F0, F1) and np.array_equal(x0, x1)
+    assert eta(A, x1, b) <= N * 1e-16
+
+
 @pytest.mark.parametrize("nrhs", [40, 64])
 def test_refinement_status_with_many_rhs(gpu, nrhs):
     """The device-side convergence test keeps ||r||, ||x|| per column and
