@@ -131,7 +131,7 @@ struct Eng {
                 } else {
                     k_panel_getrf<NB, S, 2><<<1 + rest, WG, 0, st>>>(c, k, 0);
                 }
-                k_panel_trtri<NB><<<NB / 2, WG, 0, st>>>(c, k);
+                k_panel_trtri<NB, S><<<NB / 2 + (pe ? rest : 0), WG, 0, st>>>(c, k, pe);
             }
             if (o.invnorm_estimate) k_panel_invest<NB><<<1, WG, 0, st>>>(c, k);
             else k_panel_invnorm<NB><<<(NB / B) * (NB / B), WG, 0, st>>>(c, k);

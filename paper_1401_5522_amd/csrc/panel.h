@@ -522,16 +522,17 @@ LQ_DEV void tile_norms(const Ctx &c, int k, int i, double *cs) {
 // The tile variant is held to half a SIMD's registers, so that it fits on a
 // compute unit beside a trailing-update workgroup of the previous step.
 // early = 1: after a QR step k-1 the tile's GEPP ran inside that step (its
-// last workgroup), so workgroup 0 has nothing to do.
+// last workgroup) and the tile norms run beside the triangular inverses
+// (k_panel_trtri), so the launch has nothing to do.
 template <int NB, class S, int RPT>
 __global__ __launch_bounds__(WG, RPT == 1 ? 2 : 1) void k_panel_getrf(Ctx c, int k, int early) {
     __shared__ __attribute__((aligned(16))) char smem[sizeof(GetrfSmem<NB, RPT>)];
+    if (early && c.dec[k - 1] == 0) return;
     if (blockIdx.x > 0) {
         const int i = k + (int)blockIdx.x;
         if (!c.indom(k, i)) tile_norms<NB, S>(c, k, i, (double *)smem);
         return;
     }
-    if (early && c.dec[k - 1] == 0) return;
     getrf_core<NB, S, RPT>(c, k, smem);
 }
 
@@ -580,10 +581,17 @@ LQ_DEV void trtri_col(const SRC *M, double *out, bool upper) {
     for (int r = l; r < NB; r += 64) out[r + (size_t)j * NB] = (upper ? r <= j : r >= j) ? x[r] : 0.0;
 }
 
-// Panel: grid = NB/2 workgroups; the first NB/4 invert U (into Dinv_k), the
-// rest invert L (into Linv_k), both from the GETRF copy W_k.
-template <int NB>
-__global__ __launch_bounds__(WG) void k_panel_trtri(Ctx c, int k) {
+// Panel: NB/2 workgroups; the first NB/4 invert U (into Dinv_k), the next
+// NB/4 invert L (into Linv_k), both from the GETRF copy W_k.  early = 1: the
+// launch has n-k-1 more workgroups, which compute the tile norms of the
+// criterion when step k-1 was a QR step (k_panel_getrf's otherwise).
+template <int NB, class S>
+__global__ __launch_bounds__(WG) void k_panel_trtri(Ctx c, int k, int early) {
+    if ((int)blockIdx.x >= NB / 2) {
+        __shared__ double cs[NB];
+        if (early && c.dec[k - 1] == 0) tile_norms<NB, S>(c, k, k + 1 + (int)blockIdx.x - NB / 2, cs);
+        return;
+    }
     const double *W = c.W + (size_t)k * NB * NB;
     const bool upper = blockIdx.x < NB / 4;
     trtri_col<NB, double>(W, (upper ? c.Dinv : c.Linv) + (size_t)k * NB * NB, upper);
