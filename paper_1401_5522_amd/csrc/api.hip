@@ -22,7 +22,7 @@ struct luqr_factors_s {
     int nsteps;
     std::vector<hipEvent_t> ev;  // LUQR_NPHASE + 1 per step when opts.timing is set
     std::vector<int> hdec;       // decision sequence, read once by the first GMRES refinement
-    Side side{nullptr, nullptr, nullptr, nullptr};  // lookahead stream and events (unless opts.no_lookahead)
+    Side side{nullptr, nullptr, nullptr, nullptr, nullptr};  // lookahead stream and events (unless opts.no_lookahead)
 };
 
 static int hip_rc(hipError_t e) { return e == hipSuccess ? 0 : LUQR_ERR_HIP - (int)e; }
@@ -115,6 +115,7 @@ extern "C" int luqr_factor(int64_t N, const double *dA, int64_t lda, const luqr_
     }
     if (!o->no_lookahead) {
         hipError_t he = hipStreamCreateWithFlags(&f->side.st, hipStreamNonBlocking);
+        if (he == hipSuccess) he = hipStreamCreateWithFlags(&f->side.st2, hipStreamNonBlocking);
         if (he == hipSuccess) he = hipEventCreateWithFlags(&f->side.ea, hipEventDisableTiming);
         if (he == hipSuccess) he = hipEventCreateWithFlags(&f->side.eb, hipEventDisableTiming);
         if (he == hipSuccess) he = hipEventCreateWithFlags(&f->side.el, hipEventDisableTiming);
@@ -468,6 +469,10 @@ extern "C" void luqr_destroy(luqr_factors f) {
     if (f->side.st) {
         (void)hipStreamSynchronize(f->side.st);  // its work was joined to the caller's stream
         (void)hipStreamDestroy(f->side.st);
+    }
+    if (f->side.st2) {
+        (void)hipStreamSynchronize(f->side.st2);
+        (void)hipStreamDestroy(f->side.st2);
     }
     if (f->side.ea) (void)hipEventDestroy(f->side.ea);
     if (f->side.eb) (void)hipEventDestroy(f->side.eb);

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(WG, (qr_ep_occ<NB, P>())) void k_qr_step_ep(Ctx c, 
 // Lookahead resources owned by a factorization handle: a second stream (default
 // priority) and two events that order it against the caller's stream.
 struct Side {
-    hipStream_t st;
+    hipStream_t st, st2;
     hipEvent_t ea, eb, el;
 };
 
@@ -90,8 +90,8 @@ struct Eng {
     // panel factor, norms and decision run meanwhile on st; step k+1's branch
     // kernels wait for the LU update (event el), while a QR step's R^-1 and
     // full T, which read only tile column k and write only its own buffers,
-    // may still run (the factorization ends by waiting for all of it, event
-    // eb).  The panel of step k+1 reads only tile column k+1, which the
+    // may still run on side->st2 (the factorization ends by waiting for all
+    // of it, event eb).  The panel of step k+1 reads only tile column k+1, which the
     // critical part has finished, and writes only its own per-step buffers.
     // Early GEPP (flat tree, variant A1, step k+1 without a domain, nb <=
     // 256): the QR step runs as k_qr_step_ep, and step k+1's panel launch
@@ -171,9 +171,13 @@ struct Eng {
             if (side) {
                 (void)hipEventRecord(side->ea, st);
                 (void)hipStreamWaitEvent(side->st, side->ea, 0);
-                sb = side->st;
-                if (rest > 1) k_lu_update<NB, P><<<(unsigned)rest * (rest - 1) * PER * PER, WG, 0, sb>>>(c, k, k + 2);
-                (void)hipEventRecord(side->el, sb);
+                if (rest > 1)
+                    k_lu_update<NB, P><<<(unsigned)rest * (rest - 1) * PER * PER, WG, 0, side->st>>>(c, k, k + 2);
+                (void)hipEventRecord(side->el, side->st);
+                // a QR step's R^-1 and T completion on a third stream, so that
+                // the next LU step's update is not queued behind them
+                (void)hipStreamWaitEvent(side->st2, side->ea, 0);
+                sb = side->st2;
             }
             // QR steps: R_kk after every TSQRT (A2's panel inverted the GEQRT's R for the criterion)
             k_qr_rinv<NB, S><<<NB / 4, WG, 0, sb>>>(c, k);
@@ -185,7 +189,10 @@ struct Eng {
                     k_qr_tfull<NB, P><<<n - k, WG, 0, sb>>>(c, k, 1);
                 }
             }
-            if (side) (void)hipEventRecord(side->eb, sb);
+            if (side) {  // eb: all of step k's bulk work, the LU update included
+                (void)hipStreamWaitEvent(sb, side->el, 0);
+                (void)hipEventRecord(side->eb, sb);
+            }
             if (ev) (void)hipEventRecord(ev[E * k + 5], sb);
         }
         if (side) (void)hipStreamWaitEvent(st, side->eb, 0);  // join: the factorization ends on st
