@@ -167,7 +167,8 @@ template <int NB> constexpr int upd_bt() { return NB >= 128 ? 128 : NB; }
 //   * The next chunk is loaded into registers while the current one is
 //     multiplied, then stored into the other LDS buffer: one barrier a chunk.
 //   * Four waves of 64 x 64 (4 x 4 MFMA blocks of 16 x 16); the update of C
-//     reads and writes four consecutive rows per lane (16 bytes).
+//     reads and writes four consecutive rows per lane (16 bytes), the reads
+//     issued with the first chunk's loads.
 // 74 KB of LDS and at most 256 registers: two workgroups per CU.
 constexpr int UPD_BK = 32, UPD_LD = UPD_BK + 4;
 constexpr int upd_lds_floats() { return 2 * 2 * 128 * UPD_LD; }
@@ -200,6 +201,13 @@ LQ_DEV void lu_update_f32(const float *__restrict__ Aik, const float *__restrict
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
     load(0);
+    // this lane's part of C, loaded now so that the update at the end does not wait for it
+    f4 cpre[4][4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+            cpre[mb][nb] = *(const f4 *)&C[(r0 + m0 + 16 * mb + 4 * g) + (size_t)(c0 + n0 + 16 * nb + i16) * NB];
     store(0);
     __syncthreads();
     constexpr int NCH = NB / UPD_BK;
@@ -229,10 +237,8 @@ LQ_DEV void lu_update_f32(const float *__restrict__ Aik, const float *__restrict
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            f4 *p = (f4 *)&C[(r0 + m0 + 16 * mb + 4 * g) + (size_t)(c0 + n0 + 16 * nb + i16) * NB];
-            *p = *p - acc[mb][nb];
-        }
+        for (int nb = 0; nb < 4; ++nb)
+            *(f4 *)&C[(r0 + m0 + 16 * mb + 4 * g) + (size_t)(c0 + n0 + 16 * nb + i16) * NB] = cpre[mb][nb] - acc[mb][nb];
 }
 
 // FP64 storage, nb >= 128: the same 128 x 128 x nb tile product on
