@@ -104,7 +104,7 @@ struct Eng {
         k_fill_int<<<nblk(n), WG, 0, st>>>(c.eflag, n, 0);
         k_fill_int<<<nblk(n), WG, 0, st>>>(c.dec, n, -1);
         k_fill_u32<<<nblk((int64_t)n * n), WG, 0, st>>>(c.tmax, (int64_t)n * n);
-        k_to_tiles<S><<<nblk(L.Np * L.Np), WG, 0, st>>>(A, lda, c.N, c.n, NB, (S *)c.At);
+        k_to_tiles<S><<<(unsigned)(c.n * c.n), WG, 0, st>>>(A, lda, c.N, c.n, NB, (S *)c.At);
         constexpr int B = NB < 64 ? NB : 64;
         constexpr int E = LUQR_NPHASE + 1;
         auto early_ok = [&](int k) {  // step k's GEPP may run inside QR step k-1

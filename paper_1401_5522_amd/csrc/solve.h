@@ -939,17 +939,22 @@ static __global__ void k_from_tiles(const S *At, int64_t n, int nb, int64_t N, d
     F[r + cc * ldf] = (double)At[(j * n + i) * (int64_t)nb * nb + (r % nb) + (cc % nb) * (int64_t)nb];
 }
 
-// Column-major FP64 A (lda) -> tile-major storage with identity padding.
+// Column-major FP64 A (lda) -> tile-major storage with identity padding.  One
+// workgroup per tile (blockIdx.x = i + j n); each lane converts four
+// consecutive rows of one column (nb is a multiple of 4), one 4-element store.
 template <class S>
 static __global__ void k_to_tiles(const double *A, int64_t lda, int64_t N, int64_t n, int nb, S *At) {
-    const int64_t Np = n * nb;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Np * Np) return;
-    const int64_t tile = t / ((int64_t)nb * nb), e = t % ((int64_t)nb * nb);
-    const int64_t i = tile % n, j = tile / n;
-    const int64_t r = i * nb + e % nb, cc = j * nb + e / nb;
-    double v = (r < N && cc < N) ? A[r + cc * lda] : (r == cc ? 1.0 : 0.0);
-    At[t] = (S)v;
+    struct alignas(4 * sizeof(S)) S4 { S v[4]; };
+    const int64_t tile = blockIdx.x, i = tile % n, j = tile / n;
+    S *T = At + tile * (int64_t)nb * nb;
+    for (int e = 4 * (int)threadIdx.x; e < nb * nb; e += 4 * (int)blockDim.x) {
+        const int64_t r = i * nb + e % nb, cc = j * nb + e / nb;
+        S4 o;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            o.v[u] = (S)((r + u < N && cc < N) ? A[r + u + cc * lda] : (r + u == cc ? 1.0 : 0.0));
+        *(S4 *)(T + e) = o;
+    }
 }
 
 static __global__ void k_fill_int(int *p, int64_t count, int v) {
