@@ -23,7 +23,7 @@
  *  - The library never allocates device memory: the caller provides one
  *    workspace whose size luqr_workspace_bytes reports and keeps it alive
  *    until luqr_destroy.  The library owns only the small host handle and,
- *    for the lookahead of luqr_factor, one stream and two events of its own.
+ *    for the lookahead of luqr_factor, two streams and three events of its own.
  *  - Return codes: 0 = success; -i = argument i (1-based) is invalid;
  *    LUQR_ERR_UNSUPPORTED for a valid but unimplemented combination;
  *    LUQR_ERR_HIP - e for a HIP runtime error e.  Numerical conditions
@@ -77,10 +77,11 @@ typedef struct {
                             (read back with luqr_get_step_times) */
     int32_t no_lookahead;/* 0 (default): lookahead (the Sec. 4 task graph's overlap of
                             consecutive steps): step k+1's panel factor and criterion run
-                            while step k's bulk trailing work (LU: columns k+2.., QR: R^-1
-                            and the full T factors) runs on a second stream of the
-                            library's own, joined before step k+1's branch; nonzero: every
-                            kernel in order on the caller's stream */
+                            while step k's bulk trailing work runs on two streams of the
+                            library's own: the LU update of columns k+2.., joined before
+                            step k+1's branch, and a QR step's R^-1 and full T factors,
+                            joined at the end; nonzero: every kernel in order on the
+                            caller's stream */
     int32_t domain_stride; /* 0 (default): the LU attempt pivots within the diagonal tile.
                             p > 0: within the diagonal domain (Sec. 2.1, last paragraph):
                             the panel tiles k, k+p, k+2p, ... (the tiles a node holds when
@@ -151,7 +152,7 @@ int64_t luqr_workspace_bytes(int64_t N, const luqr_opts *opts);
  * decisions and all scratch live in dWork (device, >= luqr_workspace_bytes,
  * 256-byte aligned).  On success *out receives a new handle.  Asynchronous:
  * returns once the work is enqueued on `stream` (with lookahead, part of it on
- * the handle's own stream, which is joined back to `stream` at the end, so work
+ * the handle's own streams, which are joined back to `stream` at the end, so work
  * enqueued on `stream` afterwards sees the whole factorization).  The decision
  * of step k is written on the device and read there by the LU and QR branch
  * kernels: the host never waits for it. */

@@ -61,8 +61,9 @@ __global__ __launch_bounds__(WG, (qr_ep_occ<NB, P>())) void k_qr_step_ep(Ctx c, 
     getrf_core<NB, typename Tr<P>::S, 1>(c, k + 1, smem);
 }
 
-// Lookahead resources owned by a factorization handle: a second stream (default
-// priority) and two events that order it against the caller's stream.
+// Lookahead resources owned by a factorization handle: two more streams (default
+// priority; st for the LU update, st2 for a QR step's R^-1 and T) and the
+// events that order them against the caller's stream.
 struct Side {
     hipStream_t st, st2;
     hipEvent_t ea, eb, el;

@@ -146,7 +146,7 @@ def test_step_times(gpu):
 @pytest.mark.parametrize("prec,alpha", [("fp32", 3e4), ("fp64", 3e4), ("fp32", 0.0)])
 def test_lookahead_is_a_pure_reordering(gpu, prec, alpha):
     """Lookahead (step k+1's panel during step k's bulk trailing work, on a
-    second stream) only reorders independent kernels: the factors, pivots and
+    second and a third stream) only reorders independent kernels: the factors, pivots and
     decisions must equal those of the strictly ordered run bit for bit."""
     import torch
     N, nb = 2048, 256
